@@ -1227,3 +1227,24 @@ int orc_point_floors(const orc_cfg* c, double X1, double X2, double* P) {
     apply_floors(c, &G, P);
     return 0;
 }
+
+/* Fixup rounds on given interior states (tests): code < 0 marks failed cells. */
+int64_t orc_fixups(const orc_cfg* c, double* Pout_int, const double* Pin_int, signed char* code_int) {
+    Work w;
+    int rc = work_init(&w, c);
+    if (rc) { work_free(&w); return rc; }
+    load_interior(&w.g, Pout_int, w.Ph);
+    load_interior(&w.g, Pin_int, w.Pn);
+    for (int i = 0; i < c->n1; i++)
+        for (int j = 0; j < c->n2; j++)
+            for (int k = 0; k < c->n3; k++)
+                w.code[cidx(&w.g, i, j, k)] = code_int[((size_t)i * c->n2 + j) * c->n3 + k];
+    int64_t left = fixups(&w.g, w.Ph, w.Pn, w.code);
+    store_interior(&w.g, w.Ph, Pout_int, NPR);
+    for (int i = 0; i < c->n1; i++)
+        for (int j = 0; j < c->n2; j++)
+            for (int k = 0; k < c->n3; k++)
+                code_int[((size_t)i * c->n2 + j) * c->n3 + k] = w.code[cidx(&w.g, i, j, k)];
+    work_free(&w);
+    return left;
+}

@@ -225,3 +225,16 @@ def point_floors(cfg: OrcCfg, X1: float, X2: float, P):
 
 def mc_slope(qm: float, q0: float, qp: float) -> float:
     return lib().orc_mc_slope(float(qm), float(q0), float(qp))
+
+
+def fixups(cfg: OrcCfg, Pout, Pin, code):
+    """Run the neighbour-averaging fixup rounds; returns (P, code, cells left unfixed)."""
+    Pout = _arr(Pout, (8, cfg.n1, cfg.n2, cfg.n3))
+    Pin = _arr(Pin, (8, cfg.n1, cfg.n2, cfg.n3))
+    code = np.ascontiguousarray(code, dtype=np.int8).copy()
+    L = lib()
+    L.orc_fixups.restype = ctypes.c_int64
+    L.orc_fixups.argtypes = [ctypes.POINTER(OrcCfg), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int8)]
+    left = L.orc_fixups(ctypes.byref(cfg), _dp(Pout), _dp(Pin), _bp(code))
+    return Pout, code, int(left)
