@@ -1,0 +1,151 @@
+"""Benchmark: FP64 zone-updates/s of the GR-MHD RK2 step on the 256^3 FM torus (one MI355X).
+
+A zone-update is one interior cell advanced one full RK2 step (both stages: ghosts, face fluxes,
+CFL step, flux-CT, update with source, inversion, floors, fixups).  Inputs are the seeded
+synthetic torus, resident in HBM before the timed region; W untimed warm-up steps, then exactly K
+timed steps bracketed by device synchronisation, timed with HIP events on the run's stream (which
+also bracket every kernel, for the roofline figure of the dominant kernel).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic HBM bytes per unit processed by each kernel (state/flux traffic, FP64)
+#   flux_d : per face, the primitives of one cell (8 x 8 B) + the 9-component flux written (72 B)
+#   update : per cell, three face fluxes (3 x 72 B), P^n and the stage input (2 x 64 B), P_out (64 B),
+#            method code (1 B)
+ALG_BYTES = {"flux1": 136.0, "flux2": 136.0, "flux3": 136.0, "update": 409.0, "bound": 128.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def units_per_launch(kind, n1, n2, n3):
+    if kind == "flux1":
+        return (n1 + 1) * (n2 + 2) * n3
+    if kind == "flux2":
+        return (n1 + 2) * (n2 + 1) * n3
+    if kind == "flux3":
+        return (n1 + 2) * (n2 + 2) * n3
+    if kind == "update":
+        return n1 * n2 * n3
+    if kind == "bound":
+        return (4 * (n2 + 4) + 4 * n1) * n3
+    return 0
+
+
+def cpu_baseline(cfg, P, nsteps):
+    """The oracle as it stands on the host cores, a bounded sample of the same workload."""
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    from oracle import oracle as orc
+    ocfg = orc.make_cfg(cfg)
+    t0 = time.perf_counter()
+    orc.step(ocfg, P, nsteps)
+    el = time.perf_counter() - t0
+    zones = cfg.n1 * cfg.n2 * cfg.n3
+    return {"value": zones * nsteps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsteps} RK2 steps of the full {cfg.n1}x{cfg.n2}x{cfg.n3} torus, OpenMP over cells, "
+                      f"{el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="torus3d_256x256x256")
+    ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2205_02484_amd import grmhd
+    from paper_2205_02484_amd.torus_init import make_torus
+    from paper_2205_02484_amd.workloads import WORKLOADS
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    grmhd.load()
+    cfg = WORKLOADS[args.workload]()
+    P = make_torus(cfg)
+    n1, n2, n3 = cfg.n1, cfg.n2, cfg.n3
+    zones = n1 * n2 * n3
+    stream = torch.cuda.Stream()
+    ctx = grmhd.Context(cfg, P, stream=stream)
+    print(f"[bench] {args.workload}: {zones} zones, warmup {args.warmup}", file=sys.stderr, flush=True)
+    ctx.steps(args.warmup)
+    torch.cuda.synchronize()
+    ctx.kernel_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.steps(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kt = ctx.kernel_times()
+    t, nstep, nfail = ctx.get_time()
+    ctx.kernel_timing(False)
+    ms_per_step = ms / args.steps
+    value = zones * args.steps / (ms * 1e-3)
+    print(f"[bench] {ms_per_step:.3f} ms/step, {value:.3e} ZU/s, t={t:.4f}, failures={nfail}",
+          file=sys.stderr, flush=True)
+
+    # dominant kernel by total time in the timed region
+    tot = {k: v[0] * v[1] for k, v in kt.items()}
+    dom = max((k for k in tot if k in ALG_BYTES), key=lambda k: tot[k])
+    avg_ms = kt[dom][0]
+    units = units_per_launch(dom, n1, n2, n3)
+    achieved = ALG_BYTES[dom] * units / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                "avg_ms": avg_ms, "alg_bytes_per_unit": ALG_BYTES[dom], "units_per_launch": units}
+    kernels = {k: {"avg_ms": v[0], "launches": v[1], "share": tot[k] / max(sum(tot.values()), 1e-30)}
+               for k, v in kt.items()}
+
+    out = {
+        "metric": "FP64 zone-updates/s (256^3 torus)",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Fishbone-Moncrief torus, 4% u perturbation, beta_0 = 100)",
+        "config": {"workload": args.workload, "grid": [n1, n2, n3], "zones": zones, "spin": cfg.spin,
+                   "gamma": cfg.gam, "r_out": cfg.r_out, "r_in_torus": cfg.r_in, "r_max": cfg.r_max,
+                   "cfl": cfg.cfl, "riemann": "llf"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "sim_time": t,
+        "unfixed_cells": nfail,
+    }
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print(f"[bench] CPU baseline: oracle, {args.cpu_steps} step(s)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, P, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,867 @@
+// grmhd_api.hip -- the C ABI (include/grmhd.h): run contexts, the ensemble engine, memory
+// footprints and the per-step launch chain (optionally replayed from a captured HIP graph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "grmhd.h"
+#include "grmhd_kernels.h"
+
+using namespace grmhd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return fail(GRMHD_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int BS = 256;
+enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_UPD, NK };
+// kernel kinds reported by grmhd_kernel_times
+enum { TK_BOUND = 0, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_DT, TK_UPDATE, TK_FIXUP, NTK };
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+struct Layout {
+    int64_t vs, s1, s2, gpts;
+    int64_t off_P, off_Ph, off_F[4], off_gc, off_gf1, off_gf2, off_code, off_fail, off_var, total;
+};
+
+Layout make_layout(const grmhd_grid& g) {
+    Layout L{};
+    const int act3 = g.n3 > 1;
+    L.s2 = g.n3;
+    L.s1 = (int64_t)(g.n2 + 2 * NG) * g.n3;
+    L.vs = (int64_t)(g.n1 + 2 * NG) * L.s1;
+    L.gpts = (int64_t)(g.n1 + 2 * NG) * (g.n2 + 2 * NG);
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { int64_t at = o; o += align256(bytes); return at; };
+    L.off_P = take(NPR * L.vs * 8);
+    L.off_Ph = take(NPR * L.vs * 8);
+    L.off_F[0] = -1;
+    for (int d = 1; d <= 3; ++d) {
+        const int act = d == 1 ? g.n1 > 1 : (d == 2 ? g.n2 > 1 : act3);
+        L.off_F[d] = act ? take(NCS * L.vs * 8) : -1;
+    }
+    L.off_gc = take(NGC * L.gpts * 8);
+    L.off_gf1 = take(NGF * L.gpts * 8);
+    L.off_gf2 = take(NGF * L.gpts * 8);
+    L.off_code = take(L.vs);
+    L.off_fail = take((int64_t)g.n1 * g.n2 * g.n3 * 4);
+    L.off_var = take(sizeof(RunVar));
+    L.total = o;
+    return L;
+}
+
+int validate(const grmhd_grid* g, const grmhd_params* p) {
+    if (!g || !p) return fail(GRMHD_EINVAL, "grid and params are required");
+    if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) return fail(GRMHD_EINVAL, "grid sizes must be >= 1");
+    if ((int64_t)g->n1 * g->n2 * g->n3 >= (1ll << 31)) return fail(GRMHD_EINVAL, "grid too large (>= 2^31 cells)");
+    if (g->coords != GRMHD_MKS && g->coords != GRMHD_MINKOWSKI_CART) return fail(GRMHD_EINVAL, "unknown coords");
+    if (g->coords == GRMHD_MKS) {
+        if (g->n1 < 2 || g->n2 < 2) return fail(GRMHD_EINVAL, "MKS grids need n1, n2 >= 2");
+        if (!(g->r_in > 0.0) || !(g->r_out > g->r_in)) return fail(GRMHD_EINVAL, "need 0 < r_in < r_out");
+        if (!(g->h > 0.0) || !(g->h <= 2.0)) return fail(GRMHD_EINVAL, "MKS h must be in (0, 2]");
+        if (!(std::fabs(p->spin) < 1.0)) return fail(GRMHD_EINVAL, "|spin| must be < 1");
+    } else {
+        for (int d = 0; d < 3; ++d)
+            if (!(g->xmax[d] > g->xmin[d])) return fail(GRMHD_EINVAL, "need xmin < xmax");
+    }
+    if (!(p->gam > 1.0)) return fail(GRMHD_EINVAL, "gamma must be > 1");
+    if (!(p->cfl > 0.0)) return fail(GRMHD_EINVAL, "cfl must be > 0");
+    if (p->riemann != GRMHD_LLF && p->riemann != GRMHD_HLL) return fail(GRMHD_EINVAL, "unknown riemann solver");
+    if (!(p->bsq_rho_max > 0.0) || !(p->bsq_u_max > 0.0) || !(p->gamma_max >= 1.0))
+        return fail(GRMHD_EINVAL, "ceilings must be positive, gamma_max >= 1");
+    if (!(p->c2p_tol > 0.0) || p->c2p_maxit < 0 || p->fixup_max_rounds < 0) return fail(GRMHD_EINVAL, "bad inversion controls");
+    return GRMHD_OK;
+}
+
+bool host_finite(const double* a, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+__global__ void k_count_nonfinite(const double* a, int64_t n, int* flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n && !isfinite(a[e])) atomicOr(flag, 1);
+}
+
+int device_finite(const double* a, int64_t n, hipStream_t st, bool* ok) {
+    int* d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(int)));
+    hipError_t e1 = hipMemsetAsync(d, 0, sizeof(int), st);
+    if (e1 == hipSuccess) {
+        k_count_nonfinite<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a, n, d);
+        e1 = hipGetLastError();
+    }
+    int h = 0;
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e1 == hipSuccess) e1 = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e1 != hipSuccess) return fail(GRMHD_EDEVICE, "finite check: %s", hipGetErrorString(e1));
+    *ok = h == 0;
+    return GRMHD_OK;
+}
+
+// One resident run (a context or an ensemble job).
+struct Run {
+    grmhd_grid grid{};
+    grmhd_params par{};
+    Layout L{};
+    char* mem = nullptr;
+    RunDev h{};        // host copy of the device descriptor
+    int ih = -1;       // horizon shell index
+    int64_t id = 0;
+    int64_t nsteps_req = 0;
+    bool reported = false;
+};
+
+void free_run(Run* r) {
+    if (!r) return;
+    if (r->mem) (void)hipFree(r->mem);
+    delete r;
+}
+
+int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, int on_device, hipStream_t st,
+               Run** out) {
+    int rc = validate(g, p);
+    if (rc) return rc;
+    if (!prims) return fail(GRMHD_EINVAL, "prims is NULL");
+    const int64_t ncell = (int64_t)g->n1 * g->n2 * g->n3;
+    if (!on_device && !host_finite(prims, NPR * ncell)) return fail(GRMHD_EINVAL, "prims hold NaN/Inf");
+    if (on_device) {
+        bool ok = false;
+        rc = device_finite(prims, NPR * ncell, st, &ok);
+        if (rc) return rc;
+        if (!ok) return fail(GRMHD_EINVAL, "prims hold NaN/Inf");
+    }
+    Run* r = new Run();
+    r->grid = *g;
+    r->par = *p;
+    r->L = make_layout(*g);
+    hipError_t e = hipMalloc(&r->mem, r->L.total);
+    if (e != hipSuccess) {
+        delete r;
+        (void)hipGetLastError();
+        return fail(GRMHD_ENOMEM, "device allocation of %lld bytes failed", (long long)r->L.total);
+    }
+    const Layout& L = r->L;
+    RunDev& R = r->h;
+    R.n1 = g->n1; R.n2 = g->n2; R.n3 = g->n3;
+    R.act1 = g->n1 > 1; R.act2 = g->n2 > 1; R.act3 = g->n3 > 1;
+    R.mks = g->coords == GRMHD_MKS;
+    R.riemann = p->riemann;
+    R.c2p_maxit = p->c2p_maxit;
+    R.fixup_rounds = p->fixup_max_rounds;
+    R.s1 = L.s1; R.s2 = L.s2; R.vs = L.vs;
+    R.gs1 = g->n2 + 2 * NG;
+    R.gpts = L.gpts;
+    double x1lo = 0.0;
+    R.dx[0] = 0.0;
+    if (R.mks) {
+        x1lo = std::log(g->r_in);
+        R.dx[1] = (std::log(g->r_out) - x1lo) / g->n1;
+        R.dx[2] = 1.0 / g->n2;
+        R.dx[3] = 2.0 * M_PI / g->n3;
+    } else {
+        for (int d = 1; d <= 3; ++d) {
+            const int n = d == 1 ? g->n1 : (d == 2 ? g->n2 : g->n3);
+            R.dx[d] = (g->xmax[d - 1] - g->xmin[d - 1]) / n;
+        }
+    }
+    for (int d = 0; d < 4; ++d) R.idx[d] = d ? 1.0 / R.dx[d] : 0.0;
+    R.gam = p->gam;
+    R.cfl = p->cfl;
+    R.bsq_rho_max = p->bsq_rho_max;
+    R.bsq_u_max = p->bsq_u_max;
+    R.gamma_max = p->gamma_max;
+    R.beta_ent = p->beta_entropy;
+    R.c2p_tol = p->c2p_tol;
+    R.P = (double*)(r->mem + L.off_P);
+    R.Ph = (double*)(r->mem + L.off_Ph);
+    R.F[0] = nullptr;
+    for (int d = 1; d <= 3; ++d) R.F[d] = L.off_F[d] >= 0 ? (double*)(r->mem + L.off_F[d]) : nullptr;
+    R.gc = (const double*)(r->mem + L.off_gc);
+    R.gf[0] = nullptr;
+    R.gf[1] = (const double*)(r->mem + L.off_gf1);
+    R.gf[2] = (const double*)(r->mem + L.off_gf2);
+    R.code = (int8_t*)(r->mem + L.off_code);
+    R.fail_list = (int32_t*)(r->mem + L.off_fail);
+    R.var = (RunVar*)(r->mem + L.off_var);
+
+    auto bail = [&](int code) { free_run(r); return code; };
+    if (hipMemsetAsync(r->mem, 0, L.total, st) != hipSuccess) return bail(fail(GRMHD_EDEVICE, "memset failed"));
+    GeoArgs A{};
+    A.n1 = g->n1; A.n2 = g->n2; A.mks = R.mks;
+    A.x1lo = x1lo; A.dx1 = R.dx[1]; A.dx2 = R.dx[2];
+    A.spin = p->spin; A.h = g->h;
+    A.rho_fl_coef = p->rho_fl_coef; A.rho_fl_pow = p->rho_fl_pow;
+    A.u_fl_coef = p->u_fl_coef; A.u_fl_pow = p->u_fl_pow; A.fl_abs = p->fl_abs;
+    A.gc = (double*)R.gc; A.gf1 = (double*)R.gf[1]; A.gf2 = (double*)R.gf[2];
+    launch_geometry(A, st);
+    const double* src = prims;
+    double* tmp = nullptr;
+    if (!on_device) {
+        if (hipMalloc(&tmp, NPR * ncell * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(GRMHD_ENOMEM, "staging allocation failed"));
+        }
+        if (hipMemcpyAsync(tmp, prims, NPR * ncell * 8, hipMemcpyHostToDevice, st) != hipSuccess) {
+            (void)hipFree(tmp);
+            return bail(fail(GRMHD_EDEVICE, "H2D copy failed"));
+        }
+        src = tmp;
+    }
+    launch_load(R, src, 0, st);
+    RunVar v{};
+    v.dt_req = -1.0;
+    v.steps_left = (1ll << 60);
+    v.active = 1;
+    hipError_t e2 = hipMemcpyAsync(R.var, &v, sizeof(v), hipMemcpyHostToDevice, st);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(st);
+    if (tmp) (void)hipFree(tmp);
+    if (e2 != hipSuccess) return bail(fail(GRMHD_EDEVICE, "init: %s", hipGetErrorString(e2)));
+    if (hipGetLastError() != hipSuccess) return bail(fail(GRMHD_EDEVICE, "init kernels failed"));
+    // horizon shell: first radial cell centre with r >= 1 + sqrt(1 - a^2)
+    if (R.mks) {
+        const double rh = 1.0 + std::sqrt(1.0 - p->spin * p->spin);
+        for (int i = 0; i < g->n1; ++i)
+            if (std::exp(x1lo + (i + 0.5) * R.dx[1]) >= rh) { r->ih = i; break; }
+    }
+    *out = r;
+    return GRMHD_OK;
+}
+
+int read_var(const Run* r, hipStream_t st, RunVar* v) {
+    HIPCHK(hipMemcpyAsync(v, r->h.var, sizeof(RunVar), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return GRMHD_OK;
+}
+
+// Stage-chain engine over a set of runs (one context = one run).
+struct Engine {
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    std::vector<Run*> runs;
+    RunDev* d_runs = nullptr;
+    int* d_boff = nullptr;
+    int cap = 0;
+    int nblk[NK] = {0};
+    bool dirty = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool use_graph = true;
+    // optional per-kernel event timing (plain launches, events around every kernel)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    double t_ms[NTK] = {0};
+    long long t_n[NTK] = {0};
+
+    ~Engine() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        drop_graph();
+        if (d_runs) (void)hipFree(d_runs);
+        if (d_boff) (void)hipFree(d_boff);
+        if (own_stream && st) (void)hipStreamDestroy(st);
+    }
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+    }
+    int init(void* stream) {
+        if (stream) {
+            st = (hipStream_t)stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        const char* ng = std::getenv("GRMHD_NO_GRAPH");
+        use_graph = !(ng && ng[0] == '1');
+        return GRMHD_OK;
+    }
+    static int64_t elems(const RunDev& R, int kind) {
+        const int64_t n1 = R.n1, n2 = R.n2, n3 = R.n3;
+        switch (kind) {
+            case KB_BOUND: return (4 * (n2 + 2 * NG) + 4 * n1) * n3;
+            case KB_F1: return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
+            case KB_F2: return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
+            case KB_F3: return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3 : 0;
+            default: return n1 * n2 * n3;
+        }
+    }
+    int rebuild() {
+        drop_graph();
+        const int n = (int)runs.size();
+        if (n > cap) {
+            if (d_runs) (void)hipFree(d_runs);
+            if (d_boff) (void)hipFree(d_boff);
+            d_runs = nullptr;
+            d_boff = nullptr;
+            cap = std::max(n, 8);
+            HIPCHK(hipMalloc(&d_runs, sizeof(RunDev) * cap));
+            HIPCHK(hipMalloc(&d_boff, sizeof(int) * NK * (cap + 1)));
+        }
+        std::vector<RunDev> hr(n);
+        std::vector<int> boff(NK * (cap + 1), 0);
+        for (int kind = 0; kind < NK; ++kind) {
+            int acc = 0;
+            for (int r = 0; r < n; ++r) {
+                boff[kind * (cap + 1) + r] = acc;
+                const int64_t ne = elems(runs[r]->h, kind);
+                acc += (int)((ne + BS - 1) / BS);
+            }
+            boff[kind * (cap + 1) + n] = acc;
+            nblk[kind] = acc;
+        }
+        for (int r = 0; r < n; ++r) hr[r] = runs[r]->h;
+        if (n) HIPCHK(hipMemcpyAsync(d_runs, hr.data(), sizeof(RunDev) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(d_boff, boff.data(), sizeof(int) * NK * (cap + 1), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        dirty = false;
+        return GRMHD_OK;
+    }
+    const int* boff(int kind) const { return d_boff + kind * (cap + 1); }
+    // record an event pair around the launch when timing
+    int mark(int kind) {
+        if (!timing) return GRMHD_OK;
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventRecord(e, st));
+        ev.push_back(e);
+        ev_kind.push_back(kind);
+        return GRMHD_OK;
+    }
+    int harvest() {
+        if (ev.empty()) return GRMHD_OK;
+        HIPCHK(hipEventSynchronize(ev.back()));
+        for (size_t x = 0; x + 1 < ev.size(); x += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[x], ev[x + 1]));
+            t_ms[ev_kind[x]] += ms;
+            t_n[ev_kind[x]] += 1;
+        }
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        ev_kind.clear();
+        return GRMHD_OK;
+    }
+    int enqueue_step() {
+        const int n = (int)runs.size();
+        if (!n) return GRMHD_OK;
+        const int kf[4] = {0, KB_F1, KB_F2, KB_F3};
+        for (int stage = 1; stage <= 2; ++stage) {
+            const int which = stage - 1;
+            mark(TK_BOUND);
+            launch_bound(d_runs, boff(KB_BOUND), n, nblk[KB_BOUND], which, st);
+            mark(TK_BOUND);
+            for (int d = 1; d <= 3; ++d) {
+                if (nblk[kf[d]] <= 0) continue;
+                mark(TK_FLUX1 + d - 1);
+                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, st);
+                mark(TK_FLUX1 + d - 1);
+            }
+            if (stage == 1) {
+                mark(TK_DT);
+                launch_dt(d_runs, n, st);
+                mark(TK_DT);
+            }
+            mark(TK_UPDATE);
+            launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, st);
+            mark(TK_UPDATE);
+            mark(TK_FIXUP);
+            launch_fixup(d_runs, n, stage, st);
+            mark(TK_FIXUP);
+        }
+        HIPCHK(hipGetLastError());
+        return GRMHD_OK;
+    }
+    int steps(int nsteps) {
+        if (dirty) {
+            int rc = rebuild();
+            if (rc) return rc;
+        }
+        if (runs.empty() || nsteps <= 0) return GRMHD_OK;
+        if (use_graph && !gexec && !timing) {
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_step();
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(st, &g);
+            if (rc || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                (void)hipGetLastError();
+                use_graph = false;  // fall back to plain launches
+            } else {
+                graph = g;
+                e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    drop_graph();
+                    use_graph = false;
+                }
+            }
+        }
+        if (timing) {
+            for (int s = 0; s < nsteps; ++s) {
+                int rc = enqueue_step();
+                if (rc) return rc;
+                if (ev.size() > 4096) {
+                    rc = harvest();
+                    if (rc) return rc;
+                }
+            }
+            return GRMHD_OK;
+        }
+        for (int s = 0; s < nsteps; ++s) {
+            if (use_graph && gexec) {
+                HIPCHK(hipGraphLaunch(gexec, st));
+            } else {
+                int rc = enqueue_step();
+                if (rc) return rc;
+            }
+        }
+        return GRMHD_OK;
+    }
+};
+
+}  // namespace
+
+struct grmhd_ctx {
+    Engine eng;
+    Run* run = nullptr;
+    double last_dt_req = -1.0;
+};
+
+struct grmhd_batch {
+    Engine eng;
+    std::vector<Run*> jobs;  // resident
+    int64_t budget = 0;
+    int64_t used = 0;
+    int32_t max_jobs = 0;
+    int64_t next_id = 1;
+};
+
+extern "C" {
+
+void grmhd_params_default(grmhd_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->spin = 0.0;
+    p->gam = 4.0 / 3.0;
+    p->cfl = 0.45;
+    p->riemann = GRMHD_LLF;
+    p->rho_fl_coef = 1e-5;
+    p->rho_fl_pow = -0.5;
+    p->u_fl_coef = 1e-5 / 3.0;
+    p->u_fl_pow = -2.5;
+    p->fl_abs = 1e-20;
+    p->bsq_rho_max = 50.0;
+    p->bsq_u_max = 2500.0;
+    p->gamma_max = 50.0;
+    p->beta_entropy = 1e-2;
+    p->c2p_tol = 1e-10;
+    p->c2p_maxit = 50;
+    p->fixup_max_rounds = 8;
+}
+
+const char* grmhd_last_error(void) { return g_err.c_str(); }
+
+int64_t grmhd_footprint_bytes(const grmhd_grid* grid) {
+    if (!grid || grid->n1 < 1 || grid->n2 < 1 || grid->n3 < 1) return -1;
+    return make_layout(*grid).total;
+}
+
+int grmhd_init(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_params* params, const double* prims,
+               int32_t prims_on_device, void* hip_stream) {
+    if (!out) return fail(GRMHD_EINVAL, "out is NULL");
+    *out = nullptr;
+    grmhd_ctx* c = new grmhd_ctx();
+    int rc = c->eng.init(hip_stream);
+    if (rc) { delete c; return rc; }
+    rc = create_run(grid, params, prims, prims_on_device, c->eng.st, &c->run);
+    if (rc) { delete c; return rc; }
+    c->eng.runs.push_back(c->run);
+    c->eng.dirty = true;
+    *out = c;
+    return GRMHD_OK;
+}
+
+static int set_dt_req(grmhd_ctx* c, double dt) {
+    if (std::isnan(dt)) return fail(GRMHD_EINVAL, "dt is NaN");
+    const double req = dt > 0.0 ? dt : -1.0;
+    if (req != c->last_dt_req) {
+        launch_set_var(c->run->h.var, req, -1, -1, c->eng.st);
+        HIPCHK(hipGetLastError());
+        c->last_dt_req = req;
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_steps(grmhd_ctx* c, int32_t nsteps, double dt) {
+    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(GRMHD_EINVAL, "nsteps < 0");
+    int rc = set_dt_req(c, dt);
+    if (rc) return rc;
+    return c->eng.steps(nsteps);
+}
+
+int grmhd_step(grmhd_ctx* c, double dt, double* dt_used) {
+    int rc = grmhd_steps(c, 1, dt);
+    if (rc) return rc;
+    if (dt_used) {
+        RunVar v;
+        rc = read_var(c->run, c->eng.st, &v);
+        if (rc) return rc;
+        *dt_used = v.dt;
+        if (v.nfail_last > 0) return fail(GRMHD_ENUMERIC, "%d cells left unfixed", v.nfail_last);
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_cons2prim(grmhd_ctx* c, const double* U, double* P, int8_t* code, int32_t on_device) {
+    if (!c || !U || !P) return fail(GRMHD_EINVAL, "NULL argument");
+    const RunDev& R = c->run->h;
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    hipStream_t st = c->eng.st;
+    if (on_device) {
+        launch_cons2prim(R, U, P, code, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return GRMHD_OK;
+    }
+    if (!host_finite(U, NCS * n) || !host_finite(P, NPR * n)) return fail(GRMHD_EINVAL, "inputs hold NaN/Inf");
+    double *dU = nullptr, *dP = nullptr;
+    int8_t* dc = nullptr;
+    HIPCHK(hipMalloc(&dU, NCS * n * 8));
+    hipError_t e = hipMalloc(&dP, NPR * n * 8);
+    if (e == hipSuccess) e = hipMalloc(&dc, n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dU, U, NCS * n * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dP, P, NPR * n * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        launch_cons2prim(R, dU, dP, dc, st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(P, dP, NPR * n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && code) e = hipMemcpyAsync(code, dc, n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dU);
+    (void)hipFree(dP);
+    (void)hipFree(dc);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "cons2prim: %s", hipGetErrorString(e));
+    return GRMHD_OK;
+}
+
+int grmhd_prim2cons(grmhd_ctx* c, const double* P, double* U, int32_t on_device) {
+    if (!c || !U || !P) return fail(GRMHD_EINVAL, "NULL argument");
+    const RunDev& R = c->run->h;
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    hipStream_t st = c->eng.st;
+    if (on_device) {
+        launch_prim2cons(R, P, U, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return GRMHD_OK;
+    }
+    if (!host_finite(P, NPR * n)) return fail(GRMHD_EINVAL, "P holds NaN/Inf");
+    double *dU = nullptr, *dP = nullptr;
+    HIPCHK(hipMalloc(&dU, NCS * n * 8));
+    hipError_t e = hipMalloc(&dP, NPR * n * 8);
+    if (e == hipSuccess) e = hipMemcpyAsync(dP, P, NPR * n * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        launch_prim2cons(R, dP, dU, st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(U, dU, NCS * n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dU);
+    (void)hipFree(dP);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "prim2cons: %s", hipGetErrorString(e));
+    return GRMHD_OK;
+}
+
+int grmhd_diag(grmhd_ctx* c, double* mdot, double* phi_b) {
+    if (!c || !mdot || !phi_b) return fail(GRMHD_EINVAL, "NULL argument");
+    if (!c->run->h.mks || c->run->ih < 0) return fail(GRMHD_EINVAL, "diagnostics need an MKS grid reaching the horizon");
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, 2 * sizeof(double)));
+    launch_diag(c->run->h, c->run->ih, d, c->eng.st);
+    double h[2] = {0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, c->eng.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->eng.st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "diag: %s", hipGetErrorString(e));
+    *mdot = h[0];
+    *phi_b = h[1];
+    return GRMHD_OK;
+}
+
+static int get_prims_run(Run* r, hipStream_t st, double* out, int32_t out_on_device) {
+    const RunDev& R = r->h;
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    if (out_on_device) {
+        launch_store(R, out, nullptr, nullptr, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return GRMHD_OK;
+    }
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, NPR * n * 8));
+    launch_store(R, d, nullptr, nullptr, st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d, NPR * n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "get_prims: %s", hipGetErrorString(e));
+    return GRMHD_OK;
+}
+
+int grmhd_get_prims(grmhd_ctx* c, double* out, int32_t out_on_device) {
+    if (!c || !out) return fail(GRMHD_EINVAL, "NULL argument");
+    return get_prims_run(c->run, c->eng.st, out, out_on_device);
+}
+
+int grmhd_get_time(grmhd_ctx* c, double* t, int64_t* nstep, int64_t* nfail_total) {
+    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
+    RunVar v;
+    int rc = read_var(c->run, c->eng.st, &v);
+    if (rc) return rc;
+    if (t) *t = v.t;
+    if (nstep) *nstep = v.nstep;
+    if (nfail_total) *nfail_total = v.nfail_total;
+    return GRMHD_OK;
+}
+
+int grmhd_get_codes(grmhd_ctx* c, int8_t* codes) {
+    if (!c || !codes) return fail(GRMHD_EINVAL, "NULL argument");
+    const RunDev& R = c->run->h;
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    int8_t* d = nullptr;
+    HIPCHK(hipMalloc(&d, n));
+    launch_store(R, nullptr, R.code, d, c->eng.st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(codes, d, n, hipMemcpyDeviceToHost, c->eng.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->eng.st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "get_codes: %s", hipGetErrorString(e));
+    return GRMHD_OK;
+}
+
+int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
+    if (!c || !F) return fail(GRMHD_EINVAL, "NULL argument");
+    Run* r = c->run;
+    const RunDev& R = r->h;
+    if (d < 1 || d > 3 || !(d == 1 ? R.act1 : (d == 2 ? R.act2 : R.act3)))
+        return fail(GRMHD_EINVAL, "direction %d is not active", d);
+    Engine& E = c->eng;
+    if (E.dirty) {
+        int rc = E.rebuild();
+        if (rc) return rc;
+    }
+    hipStream_t st = E.st;
+    const int kind = d == 1 ? KB_F1 : (d == 2 ? KB_F2 : KB_F3);
+    HIPCHK(hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st));
+    launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, st);
+    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, st);
+    const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
+    double* dF = nullptr;
+    HIPCHK(hipMalloc(&dF, n * 8));
+    launch_flux_out(R, d, dF, st);
+    unsigned long long bits[3] = {0, 0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(F, dF, n * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bits, R.var->cmax, sizeof(bits), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dF);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "debug_fluxes: %s", hipGetErrorString(e));
+    if (cmax) std::memcpy(cmax, &bits[d - 1], sizeof(double));
+    return GRMHD_OK;
+}
+
+int grmhd_kernel_timing(grmhd_ctx* c, int32_t on) {
+    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
+    Engine& E = c->eng;
+    int rc = E.harvest();
+    if (rc) return rc;
+    E.timing = on != 0;
+    for (int k = 0; k < NTK; ++k) {
+        E.t_ms[k] = 0.0;
+        E.t_n[k] = 0;
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_kernel_times(grmhd_ctx* c, double* avg_ms, int64_t* launches, int32_t n) {
+    if (!c || !avg_ms || n < 0) return fail(GRMHD_EINVAL, "NULL argument");
+    Engine& E = c->eng;
+    int rc = E.harvest();
+    if (rc) return rc;
+    for (int k = 0; k < n && k < NTK; ++k) {
+        avg_ms[k] = E.t_n[k] ? E.t_ms[k] / (double)E.t_n[k] : 0.0;
+        if (launches) launches[k] = E.t_n[k];
+    }
+    return GRMHD_OK;
+}
+
+void grmhd_destroy(grmhd_ctx* c) {
+    if (!c) return;
+    if (c->eng.st) (void)hipStreamSynchronize(c->eng.st);
+    free_run(c->run);
+    delete c;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* ensemble                                                                                  */
+/* ---------------------------------------------------------------------------------------- */
+
+int grmhd_batch_create(grmhd_batch** out, int64_t hbm_budget_bytes, int32_t max_jobs, void* hip_stream) {
+    if (!out) return fail(GRMHD_EINVAL, "out is NULL");
+    *out = nullptr;
+    grmhd_batch* b = new grmhd_batch();
+    int rc = b->eng.init(hip_stream);
+    if (rc) { delete b; return rc; }
+    if (hbm_budget_bytes <= 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) { delete b; return fail(GRMHD_EDEVICE, "hipMemGetInfo failed"); }
+        hbm_budget_bytes = (int64_t)(0.9 * (double)fr);
+    }
+    b->budget = hbm_budget_bytes;
+    b->max_jobs = max_jobs > 0 ? max_jobs : 1024;
+    *out = b;
+    return GRMHD_OK;
+}
+
+int grmhd_batch_admit(grmhd_batch* b, const grmhd_grid* grid, const grmhd_params* params, const double* prims,
+                      int32_t prims_on_device, int64_t nsteps, int64_t* job_id) {
+    if (!b || !grid || !job_id) return fail(GRMHD_EINVAL, "NULL argument");
+    if (nsteps < 0) return fail(GRMHD_EINVAL, "nsteps < 0");
+    const int64_t need = grmhd_footprint_bytes(grid);
+    if (need < 0) return fail(GRMHD_EINVAL, "bad grid");
+    if ((int)b->jobs.size() >= b->max_jobs || b->used + need > b->budget)
+        return fail(GRMHD_EAGAIN, "job needs %lld bytes, %lld of %lld in use", (long long)need, (long long)b->used,
+                    (long long)b->budget);
+    Run* r = nullptr;
+    int rc = create_run(grid, params, prims, prims_on_device, b->eng.st, &r);
+    if (rc) return rc;
+    r->id = b->next_id++;
+    r->nsteps_req = nsteps;
+    launch_set_var(r->h.var, -1.0, nsteps, nsteps > 0 ? 1 : 0, b->eng.st);
+    HIPCHK(hipGetLastError());
+    b->jobs.push_back(r);
+    b->used += r->L.total;
+    b->eng.runs.push_back(r);
+    b->eng.dirty = true;
+    *job_id = r->id;
+    return GRMHD_OK;
+}
+
+int grmhd_batch_advance(grmhd_batch* b, int32_t steps) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    if (steps < 0) return fail(GRMHD_EINVAL, "steps < 0");
+    return b->eng.steps(steps);
+}
+
+int grmhd_batch_poll(grmhd_batch* b, int64_t* done_ids, int32_t cap, int32_t* n_done) {
+    if (!b || !n_done) return fail(GRMHD_EINVAL, "NULL argument");
+    *n_done = 0;
+    HIPCHK(hipStreamSynchronize(b->eng.st));
+    bool changed = false;
+    for (Run* r : b->jobs) {
+        if (r->reported) continue;
+        RunVar v;
+        int rc = read_var(r, b->eng.st, &v);
+        if (rc) return rc;
+        if (v.steps_left <= 0) {
+            if (*n_done < cap && done_ids) {
+                done_ids[(*n_done)++] = r->id;
+                r->reported = true;
+                // finished jobs leave the launch tables
+                auto it = std::find(b->eng.runs.begin(), b->eng.runs.end(), r);
+                if (it != b->eng.runs.end()) { b->eng.runs.erase(it); changed = true; }
+            }
+        }
+    }
+    if (changed) b->eng.dirty = true;
+    return GRMHD_OK;
+}
+
+static Run* find_job(grmhd_batch* b, int64_t id) {
+    for (Run* r : b->jobs)
+        if (r->id == id) return r;
+    return nullptr;
+}
+
+int grmhd_batch_fetch(grmhd_batch* b, int64_t job_id, double* prims, double* t, int64_t* nstep) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    Run* r = find_job(b, job_id);
+    if (!r) return fail(GRMHD_ENOTFOUND, "no job %lld", (long long)job_id);
+    if (prims) {
+        int rc = get_prims_run(r, b->eng.st, prims, 0);
+        if (rc) return rc;
+    }
+    if (t || nstep) {
+        RunVar v;
+        int rc = read_var(r, b->eng.st, &v);
+        if (rc) return rc;
+        if (t) *t = v.t;
+        if (nstep) *nstep = v.nstep;
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_batch_release(grmhd_batch* b, int64_t job_id) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    Run* r = find_job(b, job_id);
+    if (!r) return fail(GRMHD_ENOTFOUND, "no job %lld", (long long)job_id);
+    HIPCHK(hipStreamSynchronize(b->eng.st));
+    auto it = std::find(b->eng.runs.begin(), b->eng.runs.end(), r);
+    if (it != b->eng.runs.end()) {
+        b->eng.runs.erase(it);
+        b->eng.dirty = true;
+    }
+    b->jobs.erase(std::find(b->jobs.begin(), b->jobs.end(), r));
+    b->used -= r->L.total;
+    free_run(r);
+    return GRMHD_OK;
+}
+
+int grmhd_batch_usage(grmhd_batch* b, int64_t* bytes, int32_t* jobs) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    if (bytes) *bytes = b->used;
+    if (jobs) *jobs = (int32_t)b->jobs.size();
+    return GRMHD_OK;
+}
+
+void grmhd_batch_destroy(grmhd_batch* b) {
+    if (!b) return;
+    if (b->eng.st) (void)hipStreamSynchronize(b->eng.st);
+    for (Run* r : b->jobs) free_run(r);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// grmhd_dev.h -- device-side data layout and per-point physics of the gfx950 GR-MHD stepper.
+//
+// Layout (all FP64):
+//   cell arrays   [var][i + 2][j + 2][k]   two ghost layers in X1 and X2; X3 (phi) is periodic
+//                                           and handled by index wrap, so rows stay aligned
+//   face fluxes   same layout; the flux through face i-1/2 (resp. j-1/2, k-1/2) of cell (i,j,k)
+//                 is stored at (i,j,k)
+//   geometry      [component][i + 2][j + 2]  per (r, theta) point: the metric is phi-independent
+//
+// The metric of both supported coordinate systems (MKS Kerr-Schild, flat Cartesian) has
+// g_{t2} = g_{12} = g_{23} = 0 and g^{t2} = g^{t3} = g^{12} = g^{23} = 0; only the remaining
+// components are stored and used.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grmhd {
+
+constexpr int NPR = 8;  // rho, u, u~1, u~2, u~3, B1, B2, B3
+constexpr int NCS = 9;  // sqrt(-g)(rho u^t, T^t_t, T^t_1, T^t_2, T^t_3, B1, B2, B3, S u^t)
+constexpr int NG = 2;   // ghost layers in X1 and X2
+
+// centre geometry components
+enum {
+    G_TT = 0, G_T1, G_T3, G_11, G_13, G_22, G_33,         // g_{mu nu}
+    GI_TT, GI_T1, GI_11, GI_13, GI_22, GI_33,             // g^{mu nu}
+    G_DET, G_ALPHA,
+    G_D1 = 15,   // 1/2 sqrt(-g) d_1 g_{mu nu}, 7 entries in the order tt,t1,t3,11,13,22,33
+    G_D2 = 22,   // 1/2 sqrt(-g) d_2 g_{mu nu}
+    G_RHOFL = 29, G_UFL = 30,
+    NGC = 31
+};
+constexpr int NGF = 15;  // faces carry the first 15 entries
+
+// Per-run constant description (device copy, read with scalar loads).
+struct RunVar;
+struct RunDev {
+    int32_t n1, n2, n3;
+    int32_t act1, act2, act3;
+    int32_t mks, riemann;
+    int32_t c2p_maxit, fixup_rounds;
+    int64_t s1, s2, vs;         // cell strides: i, j (k stride 1); variable stride
+    int64_t gs1, gpts;          // geometry: i stride ((n2+4)), total points
+    double dx[4], idx[4];
+    double gam, cfl;
+    double bsq_rho_max, bsq_u_max, gamma_max, beta_ent, c2p_tol;
+    double* P;                  // state P^n (updated in place by stage 2)
+    double* Ph;                 // P^{n+1/2}
+    double* F[4];               // F[1..3]
+    const double* gc;           // centre geometry
+    const double* gf[3];        // gf[1], gf[2]: X1, X2 faces
+    int8_t* code;               // method code per cell (cell layout)
+    int32_t* fail_list;         // interior linear indices of failed cells
+    RunVar* var;
+};
+
+// Per-run mutable scalars.
+struct RunVar {
+    unsigned long long cmax[3];  // bits of max c_w per direction (non-negative doubles)
+    double dt, t, dt_req;        // dt_req > 0: fixed step; <= 0: CFL
+    long long nstep, nfail_total, steps_left;
+    int32_t fail_count, active, nfail_last, pad;
+};
+
+__device__ __forceinline__ int64_t cell_index(const RunDev& R, int i, int j, int k) {
+    return (int64_t)(i + NG) * R.s1 + (int64_t)(j + NG) * R.s2 + k;
+}
+__device__ __forceinline__ int64_t geo_index(const RunDev& R, int i, int j) {
+    return (int64_t)(i + NG) * R.gs1 + (j + NG);
+}
+
+struct Geo {
+    double gtt, gt1, gt3, g11, g13, g22, g33;
+    double Gtt, Gt1, G11, G13, G22, G33;
+    double gdet, alpha;
+};
+
+__device__ __forceinline__ void load_geo(const double* __restrict__ g, int64_t np, int64_t gi, Geo& G) {
+    G.gtt = g[G_TT * np + gi];
+    G.gt1 = g[G_T1 * np + gi];
+    G.gt3 = g[G_T3 * np + gi];
+    G.g11 = g[G_11 * np + gi];
+    G.g13 = g[G_13 * np + gi];
+    G.g22 = g[G_22 * np + gi];
+    G.g33 = g[G_33 * np + gi];
+    G.Gtt = g[GI_TT * np + gi];
+    G.Gt1 = g[GI_T1 * np + gi];
+    G.G11 = g[GI_11 * np + gi];
+    G.G13 = g[GI_13 * np + gi];
+    G.G22 = g[GI_22 * np + gi];
+    G.G33 = g[GI_33 * np + gi];
+    G.gdet = g[G_DET * np + gi];
+    G.alpha = g[G_ALPHA * np + gi];
+}
+
+// 4-velocity, field 4-vector and thermodynamics of one primitive state.
+struct St {
+    double ut, u1, u2, u3;       // u^mu
+    double lt, l1, l2, l3;       // u_mu
+    double bt, b1, b2, b3;       // b^mu
+    double ct, c1, c2, c3;       // b_mu
+    double bsq, p, w, lor;
+};
+
+__device__ __forceinline__ void lower(const Geo& G, double t, double x1, double x2, double x3,
+                                      double& l0, double& l1, double& l2, double& l3) {
+    l0 = G.gtt * t + G.gt1 * x1 + G.gt3 * x3;
+    l1 = G.gt1 * t + G.g11 * x1 + G.g13 * x3;
+    l2 = G.g22 * x2;
+    l3 = G.gt3 * t + G.g13 * x1 + G.g33 * x3;
+}
+
+// u~^i -> u^mu: Gamma = sqrt(1 + g_ij u~^i u~^j), u^t = Gamma/alpha, u^i = u~^i - Gamma alpha g^{ti};
+// b^t = B^i u_i, b^i = (B^i + b^t u^i)/u^t  (Sec. 2.1).
+__device__ __forceinline__ void prim_state(const double* P, const Geo& G, double gam, St& s) {
+    const double q1 = P[2], q2 = P[3], q3 = P[4];
+    const double qsq = G.g11 * q1 * q1 + 2.0 * G.g13 * q1 * q3 + G.g22 * q2 * q2 + G.g33 * q3 * q3;
+    const double lor = sqrt(1.0 + qsq);
+    s.lor = lor;
+    s.ut = lor / G.alpha;
+    s.u1 = q1 - lor * G.alpha * G.Gt1;
+    s.u2 = q2;
+    s.u3 = q3;
+    lower(G, s.ut, s.u1, s.u2, s.u3, s.lt, s.l1, s.l2, s.l3);
+    const double B1 = P[5], B2 = P[6], B3 = P[7];
+    s.bt = B1 * s.l1 + B2 * s.l2 + B3 * s.l3;
+    const double iut = 1.0 / s.ut;
+    s.b1 = (B1 + s.bt * s.u1) * iut;
+    s.b2 = (B2 + s.bt * s.u2) * iut;
+    s.b3 = (B3 + s.bt * s.u3) * iut;
+    lower(G, s.bt, s.b1, s.b2, s.b3, s.ct, s.c1, s.c2, s.c3);
+    s.bsq = s.bt * s.ct + s.b1 * s.c1 + s.b2 * s.c2 + s.b3 * s.c3;
+    s.p = (gam - 1.0) * P[1];
+    s.w = P[0] + P[1] + s.p;
+}
+
+// Flux vector along D (D = 0: the conserved vector U).  ent = p / rho^(gam-1).
+template <int D>
+__device__ __forceinline__ void flux_of(const double* P, const St& s, const Geo& G, double ent, double* F) {
+    const double ud = D == 0 ? s.ut : (D == 1 ? s.u1 : (D == 2 ? s.u2 : s.u3));
+    const double bd = D == 0 ? s.bt : (D == 1 ? s.b1 : (D == 2 ? s.b2 : s.b3));
+    const double wb = s.w + s.bsq;
+    const double pt = s.p + 0.5 * s.bsq;
+    const double gd = G.gdet;
+    F[0] = gd * P[0] * ud;
+    F[1] = gd * (wb * ud * s.lt + (D == 0 ? pt : 0.0) - bd * s.ct);
+    F[2] = gd * (wb * ud * s.l1 + (D == 1 ? pt : 0.0) - bd * s.c1);
+    F[3] = gd * (wb * ud * s.l2 + (D == 2 ? pt : 0.0) - bd * s.c2);
+    F[4] = gd * (wb * ud * s.l3 + (D == 3 ? pt : 0.0) - bd * s.c3);
+    if (D == 0) {
+        F[5] = gd * P[5];
+        F[6] = gd * P[6];
+        F[7] = gd * P[7];
+    } else {
+        // induction flux sqrt(-g)(b^i u^d - b^d u^i)
+        F[5] = gd * (s.b1 * ud - bd * s.u1);
+        F[6] = gd * (s.b2 * ud - bd * s.u2);
+        F[7] = gd * (s.b3 * ud - bd * s.u3);
+    }
+    F[8] = gd * ent * ud;
+}
+
+// Roots of the simplified dispersion relation along D: (1-cms2)(k.u)^2 = cms2 k.k with
+// k_mu = (-omega, k_D), as c1 >= c2 in omega/k_D.
+template <int D>
+__device__ __forceinline__ void wave_speeds(const St& s, const Geo& G, double gam, double& c1, double& c2) {
+    const double cs2 = gam * s.p / s.w;
+    const double va2 = s.bsq / (s.bsq + s.w);
+    const double cms2 = va2 + cs2 * (1.0 - va2);
+    const double ud = D == 1 ? s.u1 : (D == 2 ? s.u2 : s.u3);
+    const double gtd = D == 1 ? G.Gt1 : 0.0;
+    const double gdd = D == 1 ? G.G11 : (D == 2 ? G.G22 : G.G33);
+    const double om = 1.0 - cms2;
+    const double A = om * s.ut * s.ut - cms2 * G.Gtt;
+    const double B = -2.0 * (om * s.ut * ud - cms2 * gtd);
+    const double C = om * ud * ud - cms2 * gdd;
+    double disc = B * B - 4.0 * A * C;
+    disc = disc < 0.0 ? 0.0 : disc;
+    const double sq = sqrt(disc);
+    const double i2a = 0.5 / A;
+    const double r1 = (-B + sq) * i2a;
+    const double r2 = (-B - sq) * i2a;
+    c1 = fmax(r1, r2);
+    c2 = fmin(r1, r2);
+}
+
+// Monotonised-central slope: sign(dc) min(2|dm|, 2|dp|, |dc|/2), zero at extrema.
+__device__ __forceinline__ double mc_slope(double qm, double q0, double qp) {
+    const double dm = q0 - qm, dp = qp - q0, dc = qp - qm;
+    const double lim = fmin(fmin(2.0 * fabs(dm), 2.0 * fabs(dp)), 0.5 * fabs(dc));
+    return (dm * dp > 0.0) ? copysign(lim, dc) : 0.0;
+}
+
+}  // namespace grmhd

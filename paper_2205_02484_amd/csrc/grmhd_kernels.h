@@ -1,0 +1,31 @@
+// grmhd_kernels.h -- host-side launchers of the stage kernels (internal to the library).
+#pragma once
+#include "grmhd_dev.h"
+
+namespace grmhd {
+
+struct GeoArgs {
+    int n1, n2, mks;
+    double x1lo, dx1, dx2, spin, h;
+    double rho_fl_coef, rho_fl_pow, u_fl_coef, u_fl_pow, fl_abs;
+    double* gc;
+    double* gf1;
+    double* gf2;
+};
+
+void launch_geometry(const GeoArgs& A, hipStream_t st);
+void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, hipStream_t st);
+void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
+                 hipStream_t st);
+void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
+void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st);
+void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st);
+void launch_load(const RunDev& R, const double* in, int to_half, hipStream_t st);
+void launch_store(const RunDev& R, double* out, const int8_t* code_in, int8_t* code_out, hipStream_t st);
+void launch_prim2cons(const RunDev& R, const double* P, double* U, hipStream_t st);
+void launch_cons2prim(const RunDev& R, const double* U, double* P, int8_t* code, hipStream_t st);
+void launch_diag(const RunDev& R, int ih, double* out, hipStream_t st);
+void launch_flux_out(const RunDev& R, int d, double* out, hipStream_t st);
+void launch_set_var(RunVar* V, double dt_req, long long steps_left, int active, hipStream_t st);
+
+}  // namespace grmhd

@@ -1,0 +1,820 @@
+// grmhd_kernels.hip -- gfx950 kernels of the GR-MHD stage chain.
+//
+// Every stage kernel runs over a packed block table: block b of a launch belongs to run r with
+// boff[r] <= b < boff[r+1], so one launch advances every run of an ensemble (a single run is an
+// ensemble of one).  Per-run constants come from RunDev (scalar loads, wave-uniform), per-run
+// mutable scalars from RunVar.
+//
+// Stage chain (RK2 midpoint, Sec. 2.2 of the paper):
+//   k_bound -> k_flux<1,2,3> (PLM/MC + LLF/HLL, CFL maxima) -> [k_dt] -> k_update (flux-CT,
+//   conservative update with the centred source, inversion, floors) -> k_fixup
+#include "grmhd_c2p.h"
+#include "grmhd_kernels.h"
+
+namespace grmhd {
+
+__device__ __forceinline__ int find_run(const int* __restrict__ boff, int nruns, int b) {
+    int lo = 0, hi = nruns;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (boff[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------------------------------
+// geometry (once per run): closed-form Kerr-Schild metric and inverse carried to MKS, sqrt(-g),
+// lapse, analytic d_1, d_2 of g_{mu nu} for the source, floor values
+// ------------------------------------------------------------------------------------------
+
+struct MetricPoint {
+    double g[7], gi[6], gdet, alpha, d1[7], d2[7], r;
+};
+
+__device__ void mks_point(double X1, double X2, double a, double hh, bool derivs, MetricPoint& m) {
+    const double PI = 3.14159265358979323846;
+    const double r = exp(X1);
+    const double s2pi = sin(2.0 * PI * X2), c2pi = cos(2.0 * PI * X2);
+    const double th = PI * X2 + 0.5 * (1.0 - hh) * s2pi;
+    const double dth = PI * (1.0 + (1.0 - hh) * c2pi);
+    const double d2th = -2.0 * PI * PI * (1.0 - hh) * s2pi;
+    double s, c;
+    sincos(th, &s, &c);
+    const double s2 = s * s;
+    const double a2 = a * a;
+    const double sig = r * r + a2 * c * c;
+    const double del = r * r - 2.0 * r + a2;
+    const double z = 2.0 * r / sig;
+    const double dr = r;
+    // Kerr-Schild g_{mu nu}: tt, tr, tphi, rr, rphi, thth, phiphi
+    const double K[7] = {-(1.0 - z), z, -a * z * s2, 1.0 + z, -a * (1.0 + z) * s2, sig,
+                         s2 * (sig + a2 * (1.0 + z) * s2)};
+    const double J[7] = {1.0, dr, 1.0, dr * dr, dr, dth * dth, 1.0};
+    for (int n = 0; n < 7; ++n) m.g[n] = K[n] * J[n];
+    // inverse: tt, tr, rr, rphi, thth, phiphi (KS) over the Jacobian factors
+    m.gi[0] = -(1.0 + z);
+    m.gi[1] = z / dr;
+    m.gi[2] = del / sig / (dr * dr);
+    m.gi[3] = a / sig / dr;
+    m.gi[4] = 1.0 / sig / (dth * dth);
+    m.gi[5] = 1.0 / (sig * s2);
+    m.gdet = sig * fabs(s) * dr * dth;
+    m.alpha = 1.0 / sqrt(1.0 + z);
+    m.r = r;
+    if (!derivs) return;
+    const double dsig_r = 2.0 * r, dsig_t = -2.0 * a2 * c * s;
+    const double dz_r = (2.0 * sig - 4.0 * r * r) / (sig * sig);
+    const double dz_t = -2.0 * r * dsig_t / (sig * sig);
+    const double ds2 = 2.0 * s * c;
+    const double Kr[7] = {dz_r, dz_r, -a * s2 * dz_r, dz_r, -a * s2 * dz_r, dsig_r,
+                          s2 * dsig_r + a2 * s2 * s2 * dz_r};
+    const double Kt[7] = {dz_t, dz_t, -a * (dz_t * s2 + z * ds2), dz_t, -a * (dz_t * s2 + (1.0 + z) * ds2), dsig_t,
+                          ds2 * sig + s2 * dsig_t + a2 * (dz_t * s2 * s2 + (1.0 + z) * 2.0 * s2 * ds2)};
+    // d_1 of the Jacobian factors (dr/dX1 = r): t1 -> r, 11 -> 2 r^2, 13 -> r
+    const double J1[7] = {0.0, dr, 0.0, 2.0 * dr * dr, dr, 0.0, 0.0};
+    const double J2[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 2.0 * dth * d2th, 0.0};
+    for (int n = 0; n < 7; ++n) {
+        m.d1[n] = Kr[n] * dr * J[n] + K[n] * J1[n];
+        m.d2[n] = Kt[n] * dth * J[n] + K[n] * J2[n];
+    }
+}
+
+__global__ void k_geometry(GeoArgs A) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gn2 = A.n2 + 2 * NG;
+    const int np = (A.n1 + 2 * NG) * gn2;
+    if (e >= np) return;
+    const int i = e / gn2 - NG, j = e % gn2 - NG;
+    for (int pass = 0; pass < 3; ++pass) {  // centre, X1 face, X2 face
+        double* out = pass == 0 ? A.gc : (pass == 1 ? A.gf1 : A.gf2);
+        const double fi = i + 0.5 - (pass == 1 ? 0.5 : 0.0);
+        const double fj = j + 0.5 - (pass == 2 ? 0.5 : 0.0);
+        MetricPoint m;
+        if (A.mks) {
+            mks_point(A.x1lo + fi * A.dx1, fj * A.dx2, A.spin, A.h, pass == 0, m);
+        } else {
+            for (int n = 0; n < 7; ++n) m.g[n] = m.d1[n] = m.d2[n] = 0.0;
+            m.g[0] = -1.0; m.g[3] = 1.0; m.g[5] = 1.0; m.g[6] = 1.0;
+            for (int n = 0; n < 6; ++n) m.gi[n] = 0.0;
+            m.gi[0] = -1.0; m.gi[2] = 1.0; m.gi[4] = 1.0; m.gi[5] = 1.0;
+            m.gdet = 1.0;
+            m.alpha = 1.0;
+            m.r = 1.0;
+        }
+        for (int n = 0; n < 7; ++n) out[(G_TT + n) * (int64_t)np + e] = m.g[n];
+        for (int n = 0; n < 6; ++n) out[(GI_TT + n) * (int64_t)np + e] = m.gi[n];
+        out[G_DET * (int64_t)np + e] = m.gdet;
+        out[G_ALPHA * (int64_t)np + e] = m.alpha;
+        if (pass == 0) {
+            for (int n = 0; n < 7; ++n) {
+                out[(G_D1 + n) * (int64_t)np + e] = 0.5 * m.gdet * m.d1[n];
+                out[(G_D2 + n) * (int64_t)np + e] = 0.5 * m.gdet * m.d2[n];
+            }
+            double rfl = A.fl_abs, ufl = A.fl_abs;
+            if (A.mks) {
+                rfl = fmax(rfl, A.rho_fl_coef * pow(m.r, A.rho_fl_pow));
+                ufl = fmax(ufl, A.u_fl_coef * pow(m.r, A.u_fl_pow));
+            }
+            out[G_RHOFL * (int64_t)np + e] = rfl;
+            out[G_UFL * (int64_t)np + e] = ufl;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// boundary ghosts (Sec. 4.1): radial copy keeping sqrt(-g) B^1 with no inflow at r_out, polar
+// reflection flipping u~2 and B2; flat grids are periodic.  X3 is periodic by index wrap.
+// Each ghost is computed directly from its interior source, so one launch covers corners too.
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns, int which) {
+    const int r = find_run(boff, nruns, blockIdx.x);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    const int ncolA = 4 * (n2 + 2 * NG);
+    const int64_t total = (int64_t)(ncolA + 4 * n1) * n3;
+    if (e >= total) return;
+    const int k = (int)(e % n3);
+    const int c = (int)(e / n3);
+    int i, j;
+    if (c < ncolA) {
+        const int ii = c / (n2 + 2 * NG);
+        i = ii < 2 ? ii - 2 : n1 + (ii - 2);
+        j = c % (n2 + 2 * NG) - NG;
+    } else {
+        const int cc = c - ncolA;
+        const int jj = cc / n1;
+        j = jj < 2 ? jj - 2 : n2 + (jj - 2);
+        i = cc % n1;
+    }
+    double* __restrict__ P = which ? R.Ph : R.P;
+    int is, js;
+    if (R.mks) {
+        is = i < 0 ? 0 : (i >= n1 ? n1 - 1 : i);
+        js = j < 0 ? -1 - j : (j >= n2 ? 2 * n2 - 1 - j : j);
+    } else {
+        is = (i + n1) % n1;
+        js = (j + n2) % n2;
+    }
+    const int64_t src = cell_index(R, is, js, k), dst = cell_index(R, i, j, k);
+    double v[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) v[q] = P[q * R.vs + src];
+    if (R.mks) {
+        if (i != is) {
+            const int64_t np = R.gpts;
+            v[5] *= R.gc[G_DET * np + geo_index(R, is, js)] / R.gc[G_DET * np + geo_index(R, i, js)];
+            if (i >= n1) v[2] = fmax(v[2], 0.0);
+        }
+        if (j != js) {
+            v[3] = -v[3];
+            v[6] = -v[6];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) P[q * R.vs + dst] = v[q];
+}
+
+// ------------------------------------------------------------------------------------------
+// face fluxes (Sec. 2.2): PLM/MC reconstruction of the 8 primitives, states and fluxes on both
+// sides, simplified-dispersion wave speeds, LLF (or HLL) flux, per-direction max of c_w.
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
+                                              int nruns, int which, int do_cfl) {
+    const int r = find_run(boff, nruns, blockIdx.x);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const int i0 = D == 1 ? 0 : -R.act1;
+    const int j0 = D == 2 ? 0 : -R.act2;
+    const int ni = D == 1 ? n1 + 1 : n1 + 2 * R.act1;
+    const int nj = D == 2 ? n2 + 1 : n2 + 2 * R.act2;
+    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)ni * nj * n3;
+    double cw = 0.0;
+    if (e < total) {
+        const int k = (int)(e % n3);
+        const int64_t t = e / n3;
+        const int j = (int)(t % nj) + j0;
+        const int i = (int)(t / nj) + i0;
+        const int64_t ci = cell_index(R, i, j, k);
+        double* __restrict__ F = R.F[D];
+        if (D == 2 && R.mks && (j == 0 || j == n2)) {
+#pragma unroll
+            for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.0;
+        } else {
+            const double* __restrict__ P = which ? R.Ph : R.P;
+            int64_t cm2, cm1, cp1;
+            if (D == 1) { cm2 = ci - 2 * R.s1; cm1 = ci - R.s1; cp1 = ci + R.s1; }
+            else if (D == 2) { cm2 = ci - 2 * R.s2; cm1 = ci - R.s2; cp1 = ci + R.s2; }
+            else {
+                const int64_t base = ci - k;
+                cm2 = base + (k - 2 + 2 * n3) % n3;
+                cm1 = base + (k - 1 + n3) % n3;
+                cp1 = base + (k + 1) % n3;
+            }
+            double Pl[NPR], Pr[NPR];
+#pragma unroll
+            for (int q = 0; q < NPR; ++q) {
+                const double* Pq = P + q * R.vs;
+                const double a = Pq[cm2], b = Pq[cm1], c = Pq[ci], d = Pq[cp1];
+                Pl[q] = b + 0.5 * mc_slope(a, b, c);
+                Pr[q] = c - 0.5 * mc_slope(b, c, d);
+            }
+            Geo G;
+            const double* gsrc = D == 3 ? R.gc : R.gf[D];
+            load_geo(gsrc, R.gpts, geo_index(R, i, j), G);
+            const double gam = R.gam;
+            St sl, sr;
+            prim_state(Pl, G, gam, sl);
+            prim_state(Pr, G, gam, sr);
+            const double entl = sl.p * pow(Pl[0], 1.0 - gam);
+            const double entr = sr.p * pow(Pr[0], 1.0 - gam);
+            double c1l, c2l, c1r, c2r;
+            wave_speeds<D>(sl, G, gam, c1l, c2l);
+            wave_speeds<D>(sr, G, gam, c1r, c2r);
+            const double cmax = fmax(0.0, fmax(c1r, c1l));
+            const double cmin = fmax(0.0, fmax(-c2r, -c2l));
+            const double cwf = fmax(cmax, cmin);
+            double Ul[NCS], Ur[NCS], Fl[NCS], Fr[NCS];
+            flux_of<0>(Pl, sl, G, entl, Ul);
+            flux_of<0>(Pr, sr, G, entr, Ur);
+            flux_of<D>(Pl, sl, G, entl, Fl);
+            flux_of<D>(Pr, sr, G, entr, Fr);
+            if (R.riemann == 1) {
+                const double den = cmax + cmin;
+                const double id = den > 0.0 ? 1.0 / den : 0.0;
+#pragma unroll
+                for (int q = 0; q < NCS; ++q) {
+                    const double f = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
+                                               : 0.5 * (Fl[q] + Fr[q]);
+                    F[q * R.vs + ci] = f;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
+            }
+            bool interior = true;
+            if (D != 1 && (i < 0 || i >= n1)) interior = false;
+            if (D != 2 && (j < 0 || j >= n2)) interior = false;
+            if (interior) cw = cwf;
+        }
+    }
+    if (!do_cfl) return;
+    __shared__ double red[4];
+    cw = wave_max(cw);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = cw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        unsigned long long* slot = &R.var->cmax[D - 1];
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+        const unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bits > cur) atomicMax(slot, bits);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// CFL step and per-step bookkeeping: dt = cfl / sum_d max(c_w)/dX^d (Sec. 2.2)
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_dt(const RunDev* __restrict__ runs, int nruns) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nruns) return;
+    const RunDev& R = runs[r];
+    RunVar* V = R.var;
+    if (!V->active) return;
+    double dt = V->dt_req;
+    if (dt <= 0.0) {
+        double inv = 0.0;
+        if (R.act1) inv += __longlong_as_double((long long)V->cmax[0]) * R.idx[1];
+        if (R.act2) inv += __longlong_as_double((long long)V->cmax[1]) * R.idx[2];
+        if (R.act3) inv += __longlong_as_double((long long)V->cmax[2]) * R.idx[3];
+        dt = R.cfl / inv;
+    }
+    V->dt = dt;
+    V->t += dt;
+    V->nstep += 1;
+    V->steps_left -= 1;
+    V->cmax[0] = V->cmax[1] = V->cmax[2] = 0ull;
+    V->nfail_last = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// conservative update: flux-CT (edge EMFs from four face fluxes, B fluxes replaced by the
+// average of the two edges bounding each face), U = U(P^n) + c dt (-sum dF/dX + S(P_in)),
+// inversion, floors; failed cells go to the run's fail list.
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void source_terms(const St& s, const double* __restrict__ gc, int64_t np, int64_t gi,
+                                             const Geo& G, double* S) {
+    const double wb = s.w + s.bsq;
+    const double pt = s.p + 0.5 * s.bsq;
+    // contravariant T^{kl} for the 7 stored (k,l) pairs: tt, t1, t3, 11, 13, 22, 33
+    const double T[7] = {
+        wb * s.ut * s.ut + pt * G.Gtt - s.bt * s.bt,
+        wb * s.ut * s.u1 + pt * G.Gt1 - s.bt * s.b1,
+        wb * s.ut * s.u3 - s.bt * s.b3,
+        wb * s.u1 * s.u1 + pt * G.G11 - s.b1 * s.b1,
+        wb * s.u1 * s.u3 + pt * G.G13 - s.b1 * s.b3,
+        wb * s.u2 * s.u2 + pt * G.G22 - s.b2 * s.b2,
+        wb * s.u3 * s.u3 + pt * G.G33 - s.b3 * s.b3,
+    };
+    const double mult[7] = {1.0, 2.0, 2.0, 1.0, 2.0, 1.0, 1.0};
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int n = 0; n < 7; ++n) {
+        s1 += mult[n] * T[n] * gc[(G_D1 + n) * np + gi];
+        s2 += mult[n] * T[n] * gc[(G_D2 + n) * np + gi];
+    }
+    S[0] = 0.0;
+    S[1] = s1;
+    S[2] = s2;
+    S[3] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
+                                                int nruns, int stage) {
+    const int r = find_run(boff, nruns, blockIdx.x);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n1 * n2 * n3) return;
+    const int k = (int)(e % n3);
+    const int64_t t = e / n3;
+    const int j = (int)(t % n2);
+    const int i = (int)(t / n2);
+    const int64_t ci = cell_index(R, i, j, k);
+    const int64_t vs = R.vs, s1 = R.s1, s2 = R.s2;
+    const int64_t kb = ci - k;
+    const int64_t ckm = kb + (k == 0 ? n3 - 1 : k - 1);
+    const int64_t ckp = kb + (k + 1 == n3 ? 0 : k + 1);
+    const double* __restrict__ F1 = R.F[1];
+    const double* __restrict__ F2 = R.F[2];
+    const double* __restrict__ F3 = R.F[3];
+    const bool has3 = R.act1 && R.act2, has1 = R.act2 && R.act3, has2 = R.act1 && R.act3;
+
+    // ---- L = -sum_d (F_d(+) - F_d(-)) / dX^d with flux-CT for the field components ----
+    double L[NCS];
+    {
+        const int64_t cp = ci + s1;
+        // non-field components
+#pragma unroll
+        for (int q = 0; q < NCS; ++q) L[q] = 0.0;
+        if (R.act1) {
+#pragma unroll
+            for (int q = 0; q < NCS; ++q) {
+                if (q >= 5 && q <= 7) continue;
+                L[q] -= (F1[q * vs + cp] - F1[q * vs + ci]) * R.idx[1];
+            }
+        }
+        if (R.act2) {
+            const int64_t cq = ci + s2;
+#pragma unroll
+            for (int q = 0; q < NCS; ++q) {
+                if (q >= 5 && q <= 7) continue;
+                L[q] -= (F2[q * vs + cq] - F2[q * vs + ci]) * R.idx[2];
+            }
+        }
+        if (R.act3) {
+#pragma unroll
+            for (int q = 0; q < NCS; ++q) {
+                if (q >= 5 && q <= 7) continue;
+                L[q] -= (F3[q * vs + ckp] - F3[q * vs + ci]) * R.idx[3];
+            }
+        }
+        // field components: F^d(B^d) = 0; transverse ones from edge EMFs where they exist
+        double f1b2m = 0.0, f1b2p = 0.0, f1b3m = 0.0, f1b3p = 0.0;
+        if (R.act1) {
+            f1b2m = F1[6 * vs + ci]; f1b2p = F1[6 * vs + cp];
+            f1b3m = F1[7 * vs + ci]; f1b3p = F1[7 * vs + cp];
+        }
+        double f2b1m = 0.0, f2b1p = 0.0, f2b3m = 0.0, f2b3p = 0.0;
+        double f3b1m = 0.0, f3b1p = 0.0, f3b2m = 0.0, f3b2p = 0.0;
+        if (R.act2) {
+            f2b1m = F2[5 * vs + ci]; f2b1p = F2[5 * vs + ci + s2];
+            f2b3m = F2[7 * vs + ci]; f2b3p = F2[7 * vs + ci + s2];
+        }
+        if (R.act3) {
+            f3b1m = F3[5 * vs + ci]; f3b1p = F3[5 * vs + ckp];
+            f3b2m = F3[6 * vs + ci]; f3b2p = F3[6 * vs + ckp];
+        }
+        if (has3) {
+            // E3 at the four edges (i'-1/2, j'-1/2), i' in {i,i+1}, j' in {j,j+1}
+            const double* F1b2 = F1 + 6 * vs;
+            const double* F2b1 = F2 + 5 * vs;
+            double E[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int jj = j + b;
+                    if (R.mks && (jj == 0 || jj == n2)) { E[a][b] = 0.0; continue; }
+                    const int64_t c = ci + a * s1 + b * s2;
+                    E[a][b] = 0.25 * (F1b2[c - s2] + F1b2[c] - F2b1[c - s1] - F2b1[c]);
+                }
+            f1b2m = 0.5 * (E[0][0] + E[0][1]);
+            f1b2p = 0.5 * (E[1][0] + E[1][1]);
+            f2b1m = -0.5 * (E[0][0] + E[1][0]);
+            f2b1p = -0.5 * (E[0][1] + E[1][1]);
+        }
+        if (has1) {
+            // E1 at edges (i, j'-1/2, k'-1/2)
+            const double* F2b3 = F2 + 7 * vs;
+            const double* F3b2 = F3 + 6 * vs;
+            double E[2][2];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int jj = j + b;
+                    if (R.mks && (jj == 0 || jj == n2)) { E[b][c] = 0.0; continue; }
+                    const int64_t kk = c == 0 ? ci : ckp;        // cell/face k' index
+                    const int64_t kk1 = c == 0 ? ckm : ci;       // k'-1
+                    E[b][c] = 0.25 * (F2b3[kk1 + b * s2] + F2b3[kk + b * s2] - F3b2[kk + (b - 1) * s2] - F3b2[kk + b * s2]);
+                }
+            f2b3m = 0.5 * (E[0][0] + E[0][1]);
+            f2b3p = 0.5 * (E[1][0] + E[1][1]);
+            f3b2m = -0.5 * (E[0][0] + E[1][0]);
+            f3b2p = -0.5 * (E[0][1] + E[1][1]);
+        }
+        if (has2) {
+            // E2 at edges (i'-1/2, j, k'-1/2)
+            const double* F3b1 = F3 + 5 * vs;
+            const double* F1b3 = F1 + 7 * vs;
+            double E[2][2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int64_t kk = c == 0 ? ci : ckp;
+                    const int64_t kk1 = c == 0 ? ckm : ci;
+                    E[a][c] = 0.25 * (F3b1[kk + (a - 1) * s1] + F3b1[kk + a * s1] - F1b3[kk1 + a * s1] - F1b3[kk + a * s1]);
+                }
+            f1b3m = -0.5 * (E[0][0] + E[0][1]);
+            f1b3p = -0.5 * (E[1][0] + E[1][1]);
+            f3b1m = 0.5 * (E[0][0] + E[1][0]);
+            f3b1p = 0.5 * (E[0][1] + E[1][1]);
+        }
+        if (R.act1) {
+            L[6] -= (f1b2p - f1b2m) * R.idx[1];
+            L[7] -= (f1b3p - f1b3m) * R.idx[1];
+        }
+        if (R.act2) {
+            L[5] -= (f2b1p - f2b1m) * R.idx[2];
+            L[7] -= (f2b3p - f2b3m) * R.idx[2];
+        }
+        if (R.act3) {
+            L[5] -= (f3b1p - f3b1m) * R.idx[3];
+            L[6] -= (f3b2p - f3b2m) * R.idx[3];
+        }
+    }
+
+    const int64_t gi = geo_index(R, i, j);
+    Geo G;
+    load_geo(R.gc, R.gpts, gi, G);
+    const double gam = R.gam;
+    double* __restrict__ Pn = R.P;
+    const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
+    double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
+
+    double U[NCS];
+    {
+        double P0[NPR];
+#pragma unroll
+        for (int q = 0; q < NPR; ++q) P0[q] = Pn[q * vs + ci];
+        St s0;
+        prim_state(P0, G, gam, s0);
+        flux_of<0>(P0, s0, G, s0.p * pow(P0[0], 1.0 - gam), U);
+    }
+    double Pg[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) Pg[q] = Pin[q * vs + ci];
+    {
+        St sg;
+        prim_state(Pg, G, gam, sg);
+        double S[4];
+        source_terms(sg, R.gc, R.gpts, gi, G, S);
+        L[1] += S[0];
+        L[2] += S[1];
+        L[3] += S[2];
+        L[4] += S[3];
+    }
+    const double h = (stage == 1 ? 0.5 : 1.0) * R.var->dt;
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) U[q] += h * L[q];
+
+    double P[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) P[q] = Pg[q];
+    const int m = invert_cell(U, Pg, G, R, P);
+    if (m >= 0) {
+        apply_floors(R, G, R.gc[G_RHOFL * R.gpts + gi], R.gc[G_UFL * R.gpts + gi], P);
+    } else {
+        const int pos = atomicAdd(&R.var->fail_count, 1);
+        R.fail_list[pos] = (int)e;
+    }
+    R.code[ci] = (int8_t)m;
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = P[q];
+}
+
+// ------------------------------------------------------------------------------------------
+// fixups (Sec. 2.3): Jacobi rounds of neighbour averaging of the non-field primitives over the
+// failed cells of each run -- the 4-cross average when all four are valid, else the 4-diagonal
+// average, else the average of whichever of the 8 are valid; neighbours outside the interior do
+// not count.  Cells fixed in a round become valid in the next one.  One workgroup per run.
+// ------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fixup(const RunDev* __restrict__ runs, int nruns, int stage) {
+    const RunDev& R = runs[blockIdx.x];
+    RunVar* V = R.var;
+    const bool active = V->active;
+    const int nf = active ? V->fail_count : 0;
+    __shared__ int left_s;
+    if (nf > 0) {
+        const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+        const int64_t vs = R.vs;
+        double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
+        const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
+        if (threadIdx.x == 0) left_s = nf;
+        __syncthreads();
+        for (int round = 0; round < R.fixup_rounds; ++round) {
+            if (left_s == 0) break;
+            for (int x = threadIdx.x; x < nf; x += blockDim.x) {
+                const int e = R.fail_list[x];
+                const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+                const int64_t ci = cell_index(R, i, j, k);
+                if (R.code[ci] != -1) continue;
+                const int di[8] = {1, -1, 0, 0, 1, 1, -1, -1};
+                const int dj[8] = {0, 0, 1, -1, 1, -1, 1, -1};
+                bool ok[8];
+                int nvalid = 0;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int ii = i + di[s], jj = j + dj[s];
+                    bool v = ii >= 0 && ii < n1 && jj >= 0 && jj < n2;
+                    if (v) {
+                        const int8_t c = R.code[cell_index(R, ii, jj, k)];
+                        v = c >= 0 && c <= 3;
+                    }
+                    ok[s] = v;
+                    nvalid += v;
+                }
+                if (nvalid == 0) continue;
+                const bool cross = ok[0] && ok[1] && ok[2] && ok[3];
+                const bool diag = ok[4] && ok[5] && ok[6] && ok[7];
+                double avg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                const int s0 = cross ? 0 : 4;
+                if (cross || diag) {
+                    for (int s = s0; s < s0 + 4; ++s) {
+                        const int64_t cn = cell_index(R, i + di[s], j + dj[s], k);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) avg[q] += Pout[q * vs + cn];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) avg[q] *= 0.25;
+                } else {
+                    for (int s = 0; s < 8; ++s) {
+                        if (!ok[s]) continue;
+                        const int64_t cn = cell_index(R, i + di[s], j + dj[s], k);
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) avg[q] += Pout[q * vs + cn];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) avg[q] /= (double)nvalid;
+                }
+#pragma unroll
+                for (int q = 0; q < 5; ++q) Pout[q * vs + ci] = avg[q];
+                R.code[ci] = 4;  // pending: valid from the next round on
+            }
+            __syncthreads();
+            for (int x = threadIdx.x; x < nf; x += blockDim.x) {
+                const int e = R.fail_list[x];
+                const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+                const int64_t ci = cell_index(R, i, j, k);
+                if (R.code[ci] != 4) continue;
+                R.code[ci] = 3;
+                const int64_t gi = geo_index(R, i, j);
+                Geo G;
+                load_geo(R.gc, R.gpts, gi, G);
+                double P[NPR];
+#pragma unroll
+                for (int q = 0; q < NPR; ++q) P[q] = Pout[q * vs + ci];
+                apply_floors(R, G, R.gc[G_RHOFL * R.gpts + gi], R.gc[G_UFL * R.gpts + gi], P);
+#pragma unroll
+                for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = P[q];
+                atomicSub(&left_s, 1);
+            }
+            __syncthreads();
+        }
+        int mine = 0;
+        for (int x = threadIdx.x; x < nf; x += blockDim.x) {
+            const int e = R.fail_list[x];
+            const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+            const int64_t ci = cell_index(R, i, j, k);
+            if (R.code[ci] != -1) continue;
+#pragma unroll
+            for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = Pin[q * vs + ci];
+            ++mine;
+        }
+        if (mine) {
+            atomicAdd((unsigned long long*)&V->nfail_total, (unsigned long long)mine);
+            atomicAdd(&V->nfail_last, mine);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        V->fail_count = 0;
+        if (stage == 2) V->active = V->steps_left > 0 ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// layout conversion, inversion-only, prim->cons, diagnostics
+// ------------------------------------------------------------------------------------------
+
+__global__ void k_load(RunDev R, const double* __restrict__ in, int to_half) {
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int k = (int)(e % R.n3);
+    const int64_t t = e / R.n3;
+    const int j = (int)(t % R.n2), i = (int)(t / R.n2);
+    double* P = to_half ? R.Ph : R.P;
+    const int64_t ci = cell_index(R, i, j, k);
+    for (int q = 0; q < NPR; ++q) P[q * R.vs + ci] = in[q * n + e];
+}
+
+__global__ void k_store(RunDev R, double* __restrict__ out, const int8_t* __restrict__ code_in, int8_t* __restrict__ code_out) {
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int k = (int)(e % R.n3);
+    const int64_t t = e / R.n3;
+    const int j = (int)(t % R.n2), i = (int)(t / R.n2);
+    const int64_t ci = cell_index(R, i, j, k);
+    if (out)
+        for (int q = 0; q < NPR; ++q) out[q * n + e] = R.P[q * R.vs + ci];
+    if (code_out) code_out[e] = code_in[ci];
+}
+
+__global__ void k_prim2cons(RunDev R, const double* __restrict__ Pi, double* __restrict__ Uo) {
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int64_t t = e / R.n3;
+    const int j = (int)(t % R.n2), i = (int)(t / R.n2);
+    Geo G;
+    load_geo(R.gc, R.gpts, geo_index(R, i, j), G);
+    double P[NPR], U[NCS];
+    for (int q = 0; q < NPR; ++q) P[q] = Pi[q * n + e];
+    St s;
+    prim_state(P, G, R.gam, s);
+    flux_of<0>(P, s, G, s.p * pow(P[0], 1.0 - R.gam), U);
+    for (int q = 0; q < NCS; ++q) Uo[q * n + e] = U[q];
+}
+
+__global__ void k_cons2prim(RunDev R, const double* __restrict__ Ui, double* __restrict__ Pio, int8_t* __restrict__ code) {
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int64_t t = e / R.n3;
+    const int j = (int)(t % R.n2), i = (int)(t / R.n2);
+    Geo G;
+    load_geo(R.gc, R.gpts, geo_index(R, i, j), G);
+    double U[NCS], Pg[NPR], P[NPR];
+    for (int q = 0; q < NCS; ++q) U[q] = Ui[q * n + e];
+    for (int q = 0; q < NPR; ++q) Pg[q] = P[q] = Pio[q * n + e];
+    const int m = invert_cell(U, Pg, G, R, P);
+    if (m >= 0)
+        for (int q = 0; q < NPR; ++q) Pio[q * n + e] = P[q];
+    if (code) code[e] = (int8_t)m;
+}
+
+// Horizon shell sums with a fixed-order tree, one workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_diag(RunDev R, int ih, double* __restrict__ out) {
+    __shared__ double sm[256], sf[256];
+    const int n2 = R.n2, n3 = R.n3;
+    double m = 0.0, f = 0.0;
+    for (int e = threadIdx.x; e < n2 * n3; e += 256) {
+        const int j = e / n3, k = e % n3;
+        Geo G;
+        load_geo(R.gc, R.gpts, geo_index(R, ih, j), G);
+        const int64_t ci = cell_index(R, ih, j, k);
+        double P[NPR];
+        for (int q = 0; q < NPR; ++q) P[q] = R.P[q * R.vs + ci];
+        St s;
+        prim_state(P, G, R.gam, s);
+        m += G.gdet * P[0] * s.u1 * R.dx[2] * R.dx[3];
+        f += 0.5 * G.gdet * fabs(P[5]) * R.dx[2] * R.dx[3];
+    }
+    sm[threadIdx.x] = m;
+    sf[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sm[threadIdx.x] += sm[threadIdx.x + w];
+            sf[threadIdx.x] += sf[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sm[0];
+        out[1] = sf[0];
+    }
+}
+
+// copy raw fluxes of interior faces out in [9][m1][m2][m3] order
+__global__ void k_flux_out(RunDev R, int d, double* __restrict__ out) {
+    const int m1 = R.n1 + (d == 1), m2 = R.n2 + (d == 2), m3 = R.n3 + (d == 3);
+    const int64_t n = (int64_t)m1 * m2 * m3;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int k = (int)(e % m3);
+    const int64_t t = e / m3;
+    const int j = (int)(t % m2), i = (int)(t / m2);
+    const int64_t ci = cell_index(R, i, j, k % R.n3);
+    for (int q = 0; q < NCS; ++q) out[q * n + e] = R.F[d][q * R.vs + ci];
+}
+
+__global__ void k_set_var(RunVar* V, double dt_req, long long steps_left, int active) {
+    if (threadIdx.x == 0) {
+        V->dt_req = dt_req;
+        if (steps_left >= 0) V->steps_left = steps_left;
+        if (active >= 0) V->active = active;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// host-side launchers
+// ------------------------------------------------------------------------------------------
+
+void launch_geometry(const GeoArgs& A, hipStream_t st) {
+    const int np = (A.n1 + 2 * NG) * (A.n2 + 2 * NG);
+    k_geometry<<<(np + 127) / 128, 128, 0, st>>>(A);
+}
+
+void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, hipStream_t st) {
+    if (nblocks > 0) k_bound<<<nblocks, 256, 0, st>>>(runs, boff, nruns, which);
+}
+
+void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
+                 hipStream_t st) {
+    if (nblocks <= 0) return;
+    if (d == 1) k_flux<1><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+    else if (d == 2) k_flux<2><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+    else k_flux<3><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+}
+
+void launch_dt(const RunDev* runs, int nruns, hipStream_t st) {
+    k_dt<<<(nruns + 63) / 64, 64, 0, st>>>(runs, nruns);
+}
+
+void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st) {
+    if (nblocks > 0) k_update<<<nblocks, 256, 0, st>>>(runs, boff, nruns, stage);
+}
+
+void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st) {
+    k_fixup<<<nruns, 256, 0, st>>>(runs, nruns, stage);
+}
+
+static inline unsigned nb(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_load(const RunDev& R, const double* in, int to_half, hipStream_t st) {
+    k_load<<<nb((int64_t)R.n1 * R.n2 * R.n3, 256), 256, 0, st>>>(R, in, to_half);
+}
+void launch_store(const RunDev& R, double* out, const int8_t* code_in, int8_t* code_out, hipStream_t st) {
+    k_store<<<nb((int64_t)R.n1 * R.n2 * R.n3, 256), 256, 0, st>>>(R, out, code_in, code_out);
+}
+void launch_prim2cons(const RunDev& R, const double* P, double* U, hipStream_t st) {
+    k_prim2cons<<<nb((int64_t)R.n1 * R.n2 * R.n3, 256), 256, 0, st>>>(R, P, U);
+}
+void launch_cons2prim(const RunDev& R, const double* U, double* P, int8_t* code, hipStream_t st) {
+    k_cons2prim<<<nb((int64_t)R.n1 * R.n2 * R.n3, 256), 256, 0, st>>>(R, U, P, code);
+}
+void launch_diag(const RunDev& R, int ih, double* out, hipStream_t st) {
+    k_diag<<<1, 256, 0, st>>>(R, ih, out);
+}
+void launch_flux_out(const RunDev& R, int d, double* out, hipStream_t st) {
+    const int64_t n = (int64_t)(R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
+    k_flux_out<<<nb(n, 256), 256, 0, st>>>(R, d, out);
+}
+void launch_set_var(RunVar* V, double dt_req, long long steps_left, int active, hipStream_t st) {
+    k_set_var<<<1, 64, 0, st>>>(V, dt_req, steps_left, active);
+}
+
+}  // namespace grmhd

@@ -1,0 +1,130 @@
+"""Engine-level GPU tests: graph replays equal plain launches, ensemble jobs equal solo runs, the
+ensemble admits by memory footprint, and each solo result also matches the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2205_02484_amd.torus_init import TorusConfig, make_torus
+from tests._parity import max_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02484_amd import grmhd
+    grmhd.load()
+    return grmhd
+
+
+def _cfgs():
+    return [
+        TorusConfig(n1=48, n2=32, n3=1, r_out=50.0, spin=0.5, gam=5 / 3, beta=30.0, r_max=10.0, r_in=5.0, seed=41),
+        TorusConfig(n1=40, n2=24, n3=16, r_out=60.0, spin=0.9, gam=13 / 9, beta=100.0, r_max=12.0, r_in=6.0, seed=42),
+        TorusConfig(n1=64, n2=48, n3=1, r_out=80.0, spin=0.2, gam=4 / 3, beta=300.0, r_max=16.0, r_in=8.0, seed=43),
+        TorusConfig(n1=24, n2=16, n3=8, r_out=40.0, spin=0.0, gam=5 / 3, beta=100.0, r_max=10.0, r_in=5.0, seed=44),
+    ]
+
+
+def test_graph_replays_equal_plain_launches(G):
+    c = _cfgs()[1]
+    P = make_torus(c)
+    os.environ["GRMHD_NO_GRAPH"] = "1"
+    try:
+        eager = G.Context(c, P)
+    finally:
+        os.environ.pop("GRMHD_NO_GRAPH", None)
+    graph = G.Context(c, P)
+    for rep in range(4):
+        eager.steps(3)
+        graph.steps(3)
+        a = eager.get_prims()
+        b = graph.get_prims()        # eager work and syncs between replays
+        assert np.array_equal(a, b), rep
+        assert eager.get_time() == graph.get_time()
+    eager.close()
+    graph.close()
+
+
+def test_ensemble_jobs_equal_solo_runs_and_the_oracle(G):
+    cfgs = _cfgs()
+    steps = [5, 9, 3, 7]
+    solo = []
+    for c, n in zip(cfgs, steps):
+        ctx = G.Context(c, make_torus(c))
+        ctx.steps(n)
+        solo.append((ctx.get_prims(), ctx.get_time()))
+        ctx.close()
+    b = G.Batch()
+    ids = [b.admit(c, make_torus(c), n) for c, n in zip(cfgs, steps)]
+    done = set()
+    for _ in range(20):
+        b.advance(2)
+        done |= set(b.poll())
+        if len(done) == len(ids):
+            break
+    assert done == set(ids)
+    for jid, (Ps, (ts, ns, _)) in zip(ids, solo):
+        Pb, tb, nb = b.fetch(jid)
+        assert nb == ns
+        assert tb == ts
+        assert np.array_equal(Pb, Ps)
+    b.close()
+    # and the solo runs agree with the oracle
+    for c, n, (Ps, _) in zip(cfgs[:2], steps[:2], solo[:2]):
+        Po, _, _, _ = orc.step(orc.make_cfg(c), make_torus(c), n)
+        assert max_rel_err(Ps, Po) < 1e-9
+
+
+def test_continuous_admission_midway_keeps_results(G):
+    """A job admitted while another is part-way through does not change either result."""
+    c0, c1 = _cfgs()[0], _cfgs()[3]
+    ref = []
+    for c, n in ((c0, 8), (c1, 4)):
+        ctx = G.Context(c, make_torus(c))
+        ctx.steps(n)
+        ref.append(ctx.get_prims())
+        ctx.close()
+    b = G.Batch()
+    j0 = b.admit(c0, make_torus(c0), 8)
+    b.advance(3)
+    j1 = b.admit(c1, make_torus(c1), 4)
+    done = set()
+    for _ in range(10):
+        b.advance(1)
+        done |= set(b.poll())
+    assert done == {j0, j1}
+    assert np.array_equal(b.fetch(j0)[0], ref[0])
+    assert np.array_equal(b.fetch(j1)[0], ref[1])
+    b.release(j0)
+    b.release(j1)
+    assert b.usage() == (0, 0)
+    b.close()
+
+
+def test_admission_respects_the_memory_budget(G):
+    c = _cfgs()[1]
+    need = G.footprint_bytes(c)
+    b = G.Batch(budget_bytes=int(2.5 * need))
+    assert b.admit(c, make_torus(c), 1) is not None
+    assert b.admit(c, make_torus(c), 1) is not None
+    assert b.admit(c, make_torus(c), 1) is None   # a third does not fit
+    used, jobs = b.usage()
+    assert jobs == 2 and used == 2 * need
+    b.close()
+
+
+def test_errors_are_reported_not_raised_in_c(G):
+    c = _cfgs()[0]
+    P = make_torus(c)
+    P[0, 3, 3, 0] = np.nan
+    with pytest.raises(G.GrmhdError) as ei:
+        G.Context(c, P)
+    assert ei.value.code == G.EINVAL
+    with pytest.raises(G.GrmhdError):
+        G.Context(c, make_torus(c), spin=1.5)

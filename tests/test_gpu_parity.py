@@ -1,0 +1,217 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Tolerances: the per-cell metric of tests/_parity.py must stay below 1e-12 after one RK2 step and
+below 1e-8 after ten; face fluxes, conserved variables and single inversions agree to 1e-12 or
+better.  Method-code maps must be equal (no cell of these workloads sits on a beta-switch or
+floor threshold).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2205_02484_amd.torus_init import TorusConfig, make_torus
+from paper_2205_02484_amd.workloads import torus_2d_64, torus_128x64x64, torus_256cubed
+from tests._parity import max_rel_err, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02484_amd import grmhd
+    grmhd.load()
+    return grmhd
+
+
+def _small3d(**kw):
+    base = dict(n1=40, n2=24, n3=16, r_out=60.0, gam=13.0 / 9.0, delta=0.04, seed=11, cfl=0.45)
+    base.update(kw)
+    return TorusConfig(**base)
+
+
+def _flat_box(n=(12, 10, 8)):
+    class C:
+        pass
+    c = C()
+    c.coords = "cart"
+    c.n1, c.n2, c.n3 = n
+    c.gam = 4.0 / 3.0
+    c.cfl = 0.4
+    c.xmin, c.xmax = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    x = [(np.arange(m) + 0.5) / m for m in n]
+    X, Y, Z = np.meshgrid(*x, indexing="ij")
+    s = lambda kx, ky, kz, ph: np.sin(2 * np.pi * (kx * X + ky * Y + kz * Z) + ph)
+    P = np.empty((8,) + tuple(n))
+    P[0] = 1.0 + 0.3 * s(1, 1, 0, 0.1)
+    P[1] = 0.5 + 0.2 * s(0, 1, 1, 0.7)
+    P[2] = 0.3 * s(1, 0, 1, 0.2)
+    P[3] = 0.2 * s(0, 1, 1, 1.1)
+    P[4] = 0.25 * s(1, 1, 1, 2.0)
+    P[5] = 0.4 + 0.2 * s(0, 1, 1, 0.3)
+    P[6] = 0.1 + 0.2 * s(1, 0, 1, 0.9)
+    P[7] = -0.2 + 0.1 * s(1, 1, 0, 1.4)
+    return c, P
+
+
+def _flux_scale(F):
+    return np.abs(F).reshape(9, -1).max(axis=1)
+
+
+@pytest.mark.parametrize("which", ["2d", "3d"])
+def test_face_fluxes_match_oracle(G, which):
+    c = torus_2d_64() if which == "2d" else _small3d()
+    P = make_torus(c)
+    ctx = G.Context(c, P)
+    cfg = orc.make_cfg(c)
+    for d in (1, 2, 3) if c.n3 > 1 else (1, 2):
+        Fg, cg = ctx.debug_fluxes(d)
+        Fo, co = orc.fluxes(cfg, P, d)
+        scale = _flux_scale(Fo)
+        err = np.abs(Fg - Fo) / np.maximum(np.abs(Fo), 1e-6 * scale[:, None, None, None] + 1e-300)
+        assert err.max() < 1e-12, (d, err.max())
+        assert cg == pytest.approx(co, rel=1e-13)
+    ctx.close()
+
+
+def test_prim2cons_and_inversion_match_oracle(G):
+    c = _small3d()
+    P = make_torus(c)
+    cfg = orc.make_cfg(c)
+    ctx = G.Context(c, P)
+    Ug = ctx.prim2cons(P)
+    Uo = orc.prim2cons(cfg, P)
+    assert max_rel_err(Ug, Uo) < 1e-14
+    rng = np.random.default_rng(5)
+    guess = P * (1 + 0.01 * rng.uniform(-1, 1, size=P.shape))
+    Pg, cg = ctx.cons2prim(Uo, guess)
+    Po, co = orc.cons2prim(cfg, Uo, guess)
+    assert np.array_equal(cg, co)
+    assert max_rel_err(Pg, Po) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["brent", "entropy"])
+def test_fallback_inversions_match_oracle(G, mode):
+    over = {"c2p_maxit": 0} if mode == "brent" else {"beta_entropy": 1e12}
+    c = _small3d()
+    P = make_torus(c)
+    cfg = orc.make_cfg(c, **over)
+    ctx = G.Context(c, P, **over)
+    Uo = orc.prim2cons(cfg, P)
+    Pg, cg = ctx.cons2prim(Uo, P)
+    Po, co = orc.cons2prim(cfg, Uo, P)
+    assert np.array_equal(cg, co)
+    assert set(np.unique(co)) <= {1 if mode == "brent" else 2}
+    assert max_rel_err(Pg, Po) < 1e-11
+    ctx.close()
+
+
+def _run_both(G, c, P, nsteps, dt=-1.0, **over):
+    cfg = orc.make_cfg(c, **over)
+    Po, dto, nfo, codeo = orc.step(cfg, P, nsteps, dt)
+    ctx = G.Context(c, P, **over)
+    dtg = [ctx.step(dt) for _ in range(nsteps)]
+    Pg = ctx.get_prims()
+    codeg = ctx.get_codes()
+    t, ns, nf = ctx.get_time()
+    ctx.close()
+    return Pg, Po, np.array(dtg), dto, codeg, codeo, (t, ns, nf, nfo)
+
+
+def test_one_step_2d_torus(G):
+    c = torus_2d_64()
+    P = make_torus(c)
+    Pg, Po, dtg, dto, cg, co, (t, ns, nf, nfo) = _run_both(G, c, P, 1)
+    assert dtg[0] == pytest.approx(dto[0], rel=1e-13)
+    assert np.array_equal(cg, co)
+    assert nf == nfo == 0 and ns == 1
+    assert max_rel_err(Pg, Po) < 1e-12
+
+
+def test_ten_steps_2d_torus(G):
+    c = torus_2d_64()
+    P = make_torus(c)
+    Pg, Po, dtg, dto, cg, co, (t, ns, nf, nfo) = _run_both(G, c, P, 10)
+    assert np.allclose(dtg, dto, rtol=1e-10)
+    assert t == pytest.approx(dto.sum(), rel=1e-10)
+    assert np.array_equal(cg, co)
+    assert max_rel_err(Pg, Po) < 1e-8
+
+
+@pytest.mark.parametrize("riemann", ["llf", "hll"])
+def test_small_3d_torus_steps(G, riemann):
+    c = _small3d()
+    P = make_torus(c)
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 1, riemann=riemann)
+    assert max_rel_err(Pg, Po) < 1e-12
+    assert np.array_equal(cg, co)
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 10, riemann=riemann)
+    assert max_rel_err(Pg, Po) < 1e-8
+    assert np.allclose(dtg, dto, rtol=1e-10)
+
+
+def test_ragged_3d_torus(G):
+    """Odd sizes that fill no tile evenly (block of 256 threads, 64-lane waves)."""
+    c = _small3d(n1=37, n2=19, n3=13, seed=23)
+    P = make_torus(c)
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 2)
+    assert max_rel_err(Pg, Po) < 1e-11
+
+
+def test_flat_periodic_box_steps(G):
+    c, P = _flat_box()
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 3)
+    assert max_rel_err(Pg, Po) < 1e-12
+    assert np.allclose(dtg, dto, rtol=1e-13)
+
+
+def test_flat_1d_line(G):
+    c, P = _flat_box((64, 1, 1))
+    Pg, Po, *_ = _run_both(G, c, P, 5)
+    assert max_rel_err(Pg, Po) < 1e-12
+
+
+def test_fixed_dt_and_diagnostics(G):
+    c = torus_2d_64()
+    P = make_torus(c)
+    Pg, Po, dtg, *_ = _run_both(G, c, P, 2, dt=0.01)
+    assert np.all(dtg == 0.01)
+    assert max_rel_err(Pg, Po) < 1e-12
+    cfg = orc.make_cfg(c)
+    ctx = G.Context(c, P)
+    mg, fg = ctx.diag()
+    mo, fo, ih = orc.diag(cfg, P)
+    assert mg == pytest.approx(mo, rel=1e-12)
+    assert fg == pytest.approx(fo, rel=1e-12)
+    ctx.close()
+
+
+def test_one_step_128x64x64_torus(G):
+    c = torus_128x64x64()
+    P = make_torus(c)
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 1)
+    assert dtg[0] == pytest.approx(dto[0], rel=1e-13)
+    assert np.array_equal(cg, co)
+    assert max_rel_err(Pg, Po) < 1e-12
+
+
+def test_one_step_256cubed_torus_in_bench_configuration(G):
+    """Full-size parity: the same 256^3 torus, graph-replayed launch chain and CFL step that the
+    benchmark times, one step against the oracle on every cell."""
+    c = torus_256cubed()
+    P = make_torus(c)
+    cfg = orc.make_cfg(c)
+    ctx = G.Context(c, P)
+    ctx.steps(1)
+    Pg = ctx.get_prims()
+    t, ns, nf = ctx.get_time()
+    ctx.close()
+    Po, dto, nfo, _ = orc.step(cfg, P, 1)
+    assert t == pytest.approx(dto[0], rel=1e-13)
+    assert max_rel_err(Pg, Po) < 1e-12
