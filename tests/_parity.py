@@ -1,17 +1,36 @@
 """Per-cell parity metric of the GPU path against the oracle.
 
-err = |x - y| / max(|y|, 1e-3 * max_cells |y_var|) per cell and variable (0 when both are 0):
-relative where a variable is not small compared with its own range, absolute at 1e-3 of that
-range otherwise (floors and the atmosphere hold values many decades below the torus)."""
+For primitive states P = (rho, u, u~1, u~2, u~3, B1, B2, B3):
+
+    err = |x - y| / max(|y|, 1e-3 * S_k)      (0 where x == y)
+
+with S_k the scale of variable k over all cells: max|rho| for rho, max|u| for u, the largest
+component of the field for every B^i (the three components are one vector), and for every u~^i
+the largest velocity component but at least 1 (u~ is a spatial 4-velocity in units of c, so an
+absolute difference of a few ulp of 1 is the rounding limit however slow the local flow is).
+Relative where a quantity is not tiny against its own scale, absolute at 1e-3 of that scale
+otherwise: floors and the atmosphere hold values many decades below the torus, where the
+inversion is ill-conditioned and no FP64 implementation can fix more digits.
+
+For conserved vectors and fluxes each of the 9 components is its own scale."""
 import numpy as np
+
+
+def _scales(y):
+    nv = y.shape[0]
+    sc = np.abs(y).reshape(nv, -1).max(axis=1)
+    if nv == 8:
+        sc[2:5] = max(sc[2:5].max(), 1.0)
+        sc[5:8] = sc[5:8].max()
+    return sc
 
 
 def rel_err(x, y):
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     nv = y.shape[0]
-    scale = np.abs(y).reshape(nv, -1).max(axis=1)
-    den = np.maximum(np.abs(y), 1e-3 * scale.reshape((nv,) + (1,) * (y.ndim - 1)))
+    sc = _scales(y)
+    den = np.maximum(np.abs(y), 1e-3 * sc.reshape((nv,) + (1,) * (y.ndim - 1)))
     with np.errstate(invalid="ignore", divide="ignore"):
         e = np.where(den > 0, np.abs(x - y) / np.where(den > 0, den, 1.0), np.where(x == y, 0.0, np.inf))
     return e
@@ -19,3 +38,16 @@ def rel_err(x, y):
 
 def max_rel_err(x, y):
     return float(rel_err(x, y).max())
+
+
+def scaled_abs_err(x, y):
+    """max over cells of |x - y| / max|y_k| per component k (fluxes, conserved vectors)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    nv = y.shape[0]
+    sc = np.abs(y).reshape(nv, -1).max(axis=1)
+    # a component that vanishes identically (e.g. F^d(B^d)) is measured against the largest one
+    sc = np.where(sc > 0, sc, sc.max())
+    d = np.abs(x - y).reshape(nv, -1).max(axis=1)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return float(np.where(sc > 0, d / np.where(sc > 0, sc, 1.0), np.where(d == 0, 0.0, np.inf)).max())

@@ -27,7 +27,7 @@ def _cfgs():
         TorusConfig(n1=48, n2=32, n3=1, r_out=50.0, spin=0.5, gam=5 / 3, beta=30.0, r_max=10.0, r_in=5.0, seed=41),
         TorusConfig(n1=40, n2=24, n3=16, r_out=60.0, spin=0.9, gam=13 / 9, beta=100.0, r_max=12.0, r_in=6.0, seed=42),
         TorusConfig(n1=64, n2=48, n3=1, r_out=80.0, spin=0.2, gam=4 / 3, beta=300.0, r_max=16.0, r_in=8.0, seed=43),
-        TorusConfig(n1=24, n2=16, n3=8, r_out=40.0, spin=0.0, gam=5 / 3, beta=100.0, r_max=10.0, r_in=5.0, seed=44),
+        TorusConfig(n1=24, n2=16, n3=8, r_out=40.0, spin=0.3, gam=5 / 3, beta=100.0, r_max=12.0, r_in=6.0, seed=44),
     ]
 
 
@@ -127,4 +127,4 @@ def test_errors_are_reported_not_raised_in_c(G):
         G.Context(c, P)
     assert ei.value.code == G.EINVAL
     with pytest.raises(G.GrmhdError):
-        G.Context(c, make_torus(c), spin=1.5)
+        G.Context(c, make_torus(c), spin=1.5, r_in_grid=1.0)

@@ -1,9 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
 
 Tolerances: the per-cell metric of tests/_parity.py must stay below 1e-12 after one RK2 step and
-below 1e-8 after ten; face fluxes, conserved variables and single inversions agree to 1e-12 or
-better.  Method-code maps must be equal (no cell of these workloads sits on a beta-switch or
-floor threshold).
+below 1e-8 after ten.  Face fluxes agree to 1e-12 of each component's largest value: in the torus
+the Lax-Friedrichs flux is a small difference of terms (sqrt(-g) rho u^t ~ 3e3 times a wave
+speed ~ 5e-3) that can be ~40 times larger than the flux itself, so a per-face relative bound would
+measure that cancellation, not the code.  Method-code maps must be equal (no cell of these
+workloads sits on a beta-switch or floor threshold).
 """
 import math
 import os
@@ -14,7 +16,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2205_02484_amd.torus_init import TorusConfig, make_torus
 from paper_2205_02484_amd.workloads import torus_2d_64, torus_128x64x64, torus_256cubed
-from tests._parity import max_rel_err, rel_err
+from tests._parity import max_rel_err, rel_err, scaled_abs_err
 
 pytestmark = pytest.mark.gpu
 
@@ -59,10 +61,6 @@ def _flat_box(n=(12, 10, 8)):
     return c, P
 
 
-def _flux_scale(F):
-    return np.abs(F).reshape(9, -1).max(axis=1)
-
-
 @pytest.mark.parametrize("which", ["2d", "3d"])
 def test_face_fluxes_match_oracle(G, which):
     c = torus_2d_64() if which == "2d" else _small3d()
@@ -72,9 +70,7 @@ def test_face_fluxes_match_oracle(G, which):
     for d in (1, 2, 3) if c.n3 > 1 else (1, 2):
         Fg, cg = ctx.debug_fluxes(d)
         Fo, co = orc.fluxes(cfg, P, d)
-        scale = _flux_scale(Fo)
-        err = np.abs(Fg - Fo) / np.maximum(np.abs(Fo), 1e-6 * scale[:, None, None, None] + 1e-300)
-        assert err.max() < 1e-12, (d, err.max())
+        assert scaled_abs_err(Fg, Fo) < 1e-12, d
         assert cg == pytest.approx(co, rel=1e-13)
     ctx.close()
 
@@ -86,7 +82,7 @@ def test_prim2cons_and_inversion_match_oracle(G):
     ctx = G.Context(c, P)
     Ug = ctx.prim2cons(P)
     Uo = orc.prim2cons(cfg, P)
-    assert max_rel_err(Ug, Uo) < 1e-14
+    assert scaled_abs_err(Ug, Uo) < 1e-14
     rng = np.random.default_rng(5)
     guess = P * (1 + 0.01 * rng.uniform(-1, 1, size=P.shape))
     Pg, cg = ctx.cons2prim(Uo, guess)
@@ -107,8 +103,9 @@ def test_fallback_inversions_match_oracle(G, mode):
     Pg, cg = ctx.cons2prim(Uo, P)
     Po, co = orc.cons2prim(cfg, Uo, P)
     assert np.array_equal(cg, co)
-    assert set(np.unique(co)) <= {1 if mode == "brent" else 2}
-    assert max_rel_err(Pg, Po) < 1e-11
+    # cells without field keep beta = infinity and stay on the energy equation
+    assert (1 if mode == "brent" else 2) in set(np.unique(co))
+    assert max_rel_err(Pg, Po) < 1e-12
     ctx.close()
 
 
@@ -160,8 +157,10 @@ def test_ragged_3d_torus(G):
     """Odd sizes that fill no tile evenly (block of 256 threads, 64-lane waves)."""
     c = _small3d(n1=37, n2=19, n3=13, seed=23)
     P = make_torus(c)
-    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 2)
-    assert max_rel_err(Pg, Po) < 1e-11
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 1)
+    assert max_rel_err(Pg, Po) < 1e-12
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 10)
+    assert max_rel_err(Pg, Po) < 1e-8
 
 
 def test_flat_periodic_box_steps(G):
