@@ -125,7 +125,8 @@ int grmhd_debug_fluxes(grmhd_ctx* ctx, int32_t d, double* F, double* cmax);
 /* Measurement: with timing on, later steps run as plain launches with a HIP event pair recorded
  * on the context's stream around every kernel.  grmhd_kernel_times waits for them and returns
  * the average duration (ms) and launch count per kernel kind, in this order: 0 boundary ghosts,
- * 1-3 face fluxes X1/X2/X3, 4 CFL step, 5 update+inversion, 6 fixup.  Turning timing on or off
+ * 1-3 face fluxes X1/X2/X3, 4 CFL step, 5 update + Newton-Raphson inversion, 6 fixup,
+ * 7 full inversion of the cells the fast path hands over (beta switch, Brent, entropy, ceilings).  Turning timing on or off
  * clears the accumulated figures. */
 int grmhd_kernel_timing(grmhd_ctx* ctx, int32_t on);
 int grmhd_kernel_times(grmhd_ctx* ctx, double* avg_ms, int64_t* launches, int32_t n);

@@ -39,13 +39,13 @@ int fail(int code, const char* fmt, ...) {
 constexpr int BS = 256;
 enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_UPD, NK };
 // kernel kinds reported by grmhd_kernel_times
-enum { TK_BOUND = 0, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_DT, TK_UPDATE, TK_FIXUP, NTK };
+enum { TK_BOUND = 0, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_DT, TK_UPDATE, TK_FIXUP, TK_SLOW, NTK };
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 struct Layout {
     int64_t vs, s1, s2, gpts;
-    int64_t off_P, off_Ph, off_F[4], off_gc, off_gf1, off_gf2, off_code, off_fail, off_var, total;
+    int64_t off_P, off_Ph, off_F[4], off_gc, off_gf1, off_gf2, off_code, off_fail, off_slow, off_var, total;
 };
 
 Layout make_layout(const grmhd_grid& g) {
@@ -69,6 +69,7 @@ Layout make_layout(const grmhd_grid& g) {
     L.off_gf2 = take(NGF * L.gpts * 8);
     L.off_code = take(L.vs);
     L.off_fail = take((int64_t)g.n1 * g.n2 * g.n3 * 4);
+    L.off_slow = take((int64_t)g.n1 * g.n2 * g.n3 * 4);
     L.off_var = take(sizeof(RunVar));
     L.total = o;
     return L;
@@ -209,6 +210,8 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.gf[2] = (const double*)(r->mem + L.off_gf2);
     R.code = (int8_t*)(r->mem + L.off_code);
     R.fail_list = (int32_t*)(r->mem + L.off_fail);
+    R.slow_list = (int32_t*)(r->mem + L.off_slow);
+    R.geo_uniform = (g->n3 % 64) == 0;
     R.var = (RunVar*)(r->mem + L.off_var);
 
     auto bail = [&](int code) { free_run(r); return code; };
@@ -393,6 +396,9 @@ struct Engine {
             mark(TK_UPDATE);
             launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, st);
             mark(TK_UPDATE);
+            mark(TK_SLOW);
+            launch_update_slow(d_runs, n, stage, st);
+            mark(TK_SLOW);
             mark(TK_FIXUP);
             launch_fixup(d_runs, n, stage, st);
             mark(TK_FIXUP);

@@ -39,6 +39,8 @@ struct RunDev {
     int32_t act1, act2, act3;
     int32_t mks, riemann;
     int32_t c2p_maxit, fixup_rounds;
+    int32_t geo_uniform;        // n3 % 64 == 0: a wave's 64 cells share (r, theta)
+    int32_t pad_;
     int64_t s1, s2, vs;         // cell strides: i, j (k stride 1); variable stride
     int64_t gs1, gpts;          // geometry: i stride ((n2+4)), total points
     double dx[4], idx[4];
@@ -51,6 +53,7 @@ struct RunDev {
     const double* gf[3];        // gf[1], gf[2]: X1, X2 faces
     int8_t* code;               // method code per cell (cell layout)
     int32_t* fail_list;         // interior linear indices of failed cells
+    int32_t* slow_list;         // cells the fast inversion path hands to the full procedure
     RunVar* var;
 };
 
@@ -59,7 +62,7 @@ struct RunVar {
     unsigned long long cmax[3];  // bits of max c_w per direction (non-negative doubles)
     double dt, t, dt_req;        // dt_req > 0: fixed step; <= 0: CFL
     long long nstep, nfail_total, steps_left;
-    int32_t fail_count, active, nfail_last, pad;
+    int32_t fail_count, active, nfail_last, slow_count;
 };
 
 __device__ __forceinline__ int64_t cell_index(const RunDev& R, int i, int j, int k) {

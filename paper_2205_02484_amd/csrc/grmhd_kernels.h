@@ -19,6 +19,7 @@ void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblo
                  hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
 void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st);
+void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st);
 void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st);
 void launch_load(const RunDev& R, const double* in, int to_half, hipStream_t st);
 void launch_store(const RunDev& R, double* out, const int8_t* code_in, int8_t* code_out, hipStream_t st);

@@ -188,6 +188,80 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// One face: returns c_w (0 when the face does not count for the CFL step).  The left state's
+// conserved vector, flux and speeds are finished before the right state is formed, and the
+// right state's components are folded into the Riemann flux as they are produced, which keeps
+// the live register set to one state plus two 9-vectors.
+template <int D, bool UNI>
+__device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k, int which) {
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const int64_t ci = cell_index(R, i, j, k);
+    double* __restrict__ F = R.F[D];
+    if (D == 2 && R.mks && (j == 0 || j == n2)) {
+#pragma unroll
+        for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.0;
+        return 0.0;
+    }
+    const double* __restrict__ P = which ? R.Ph : R.P;
+    int64_t cm2, cm1, cp1;
+    if (D == 1) { cm2 = ci - 2 * R.s1; cm1 = ci - R.s1; cp1 = ci + R.s1; }
+    else if (D == 2) { cm2 = ci - 2 * R.s2; cm1 = ci - R.s2; cp1 = ci + R.s2; }
+    else {
+        const int64_t base = ci - k;
+        cm2 = base + (k >= 2 ? k - 2 : k - 2 + n3);
+        cm1 = base + (k >= 1 ? k - 1 : k - 1 + n3);
+        cp1 = base + (k + 1 < n3 ? k + 1 : k + 1 - n3);
+    }
+    double Pl[NPR], Pr[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) {
+        const double* Pq = P + q * R.vs;
+        const double a = Pq[cm2], b = Pq[cm1], c = Pq[ci], d = Pq[cp1];
+        Pl[q] = b + 0.5 * mc_slope(a, b, c);
+        Pr[q] = c - 0.5 * mc_slope(b, c, d);
+    }
+    int64_t gi = geo_index(R, i, j);
+    if (UNI) gi = __builtin_amdgcn_readfirstlane((int)gi);
+    Geo G;
+    load_geo(D == 3 ? R.gc : R.gf[D], R.gpts, gi, G);
+    const double gam = R.gam;
+    double Ul[NCS], Fl[NCS];
+    double c1l, c2l;
+    {
+        St s;
+        prim_state(Pl, G, gam, s);
+        const double ent = s.p * pow(Pl[0], 1.0 - gam);
+        wave_speeds<D>(s, G, gam, c1l, c2l);
+        flux_of<0>(Pl, s, G, ent, Ul);
+        flux_of<D>(Pl, s, G, ent, Fl);
+    }
+    St s;
+    prim_state(Pr, G, gam, s);
+    const double entr = s.p * pow(Pr[0], 1.0 - gam);
+    double c1r, c2r;
+    wave_speeds<D>(s, G, gam, c1r, c2r);
+    const double cmax = fmax(0.0, fmax(c1r, c1l));
+    const double cmin = fmax(0.0, fmax(-c2r, -c2l));
+    const double cwf = fmax(cmax, cmin);
+    double Ur[NCS], Fr[NCS];
+    flux_of<0>(Pr, s, G, entr, Ur);
+    flux_of<D>(Pr, s, G, entr, Fr);
+    if (R.riemann == 1) {
+        const double den = cmax + cmin;
+        const double id = den > 0.0 ? 1.0 / den : 0.0;
+#pragma unroll
+        for (int q = 0; q < NCS; ++q)
+            F[q * R.vs + ci] = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
+                                         : 0.5 * (Fl[q] + Fr[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
+    }
+    if (D != 1 && (i < 0 || i >= n1)) return 0.0;
+    if (D != 2 && (j < 0 || j >= n2)) return 0.0;
+    return cwf;
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                               int nruns, int which, int do_cfl) {
@@ -207,68 +281,7 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
         const int64_t t = e / n3;
         const int j = (int)(t % nj) + j0;
         const int i = (int)(t / nj) + i0;
-        const int64_t ci = cell_index(R, i, j, k);
-        double* __restrict__ F = R.F[D];
-        if (D == 2 && R.mks && (j == 0 || j == n2)) {
-#pragma unroll
-            for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.0;
-        } else {
-            const double* __restrict__ P = which ? R.Ph : R.P;
-            int64_t cm2, cm1, cp1;
-            if (D == 1) { cm2 = ci - 2 * R.s1; cm1 = ci - R.s1; cp1 = ci + R.s1; }
-            else if (D == 2) { cm2 = ci - 2 * R.s2; cm1 = ci - R.s2; cp1 = ci + R.s2; }
-            else {
-                const int64_t base = ci - k;
-                cm2 = base + (k - 2 + 2 * n3) % n3;
-                cm1 = base + (k - 1 + n3) % n3;
-                cp1 = base + (k + 1) % n3;
-            }
-            double Pl[NPR], Pr[NPR];
-#pragma unroll
-            for (int q = 0; q < NPR; ++q) {
-                const double* Pq = P + q * R.vs;
-                const double a = Pq[cm2], b = Pq[cm1], c = Pq[ci], d = Pq[cp1];
-                Pl[q] = b + 0.5 * mc_slope(a, b, c);
-                Pr[q] = c - 0.5 * mc_slope(b, c, d);
-            }
-            Geo G;
-            const double* gsrc = D == 3 ? R.gc : R.gf[D];
-            load_geo(gsrc, R.gpts, geo_index(R, i, j), G);
-            const double gam = R.gam;
-            St sl, sr;
-            prim_state(Pl, G, gam, sl);
-            prim_state(Pr, G, gam, sr);
-            const double entl = sl.p * pow(Pl[0], 1.0 - gam);
-            const double entr = sr.p * pow(Pr[0], 1.0 - gam);
-            double c1l, c2l, c1r, c2r;
-            wave_speeds<D>(sl, G, gam, c1l, c2l);
-            wave_speeds<D>(sr, G, gam, c1r, c2r);
-            const double cmax = fmax(0.0, fmax(c1r, c1l));
-            const double cmin = fmax(0.0, fmax(-c2r, -c2l));
-            const double cwf = fmax(cmax, cmin);
-            double Ul[NCS], Ur[NCS], Fl[NCS], Fr[NCS];
-            flux_of<0>(Pl, sl, G, entl, Ul);
-            flux_of<0>(Pr, sr, G, entr, Ur);
-            flux_of<D>(Pl, sl, G, entl, Fl);
-            flux_of<D>(Pr, sr, G, entr, Fr);
-            if (R.riemann == 1) {
-                const double den = cmax + cmin;
-                const double id = den > 0.0 ? 1.0 / den : 0.0;
-#pragma unroll
-                for (int q = 0; q < NCS; ++q) {
-                    const double f = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
-                                               : 0.5 * (Fl[q] + Fr[q]);
-                    F[q * R.vs + ci] = f;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
-            }
-            bool interior = true;
-            if (D != 1 && (i < 0 || i >= n1)) interior = false;
-            if (D != 2 && (j < 0 || j >= n2)) interior = false;
-            if (interior) cw = cwf;
-        }
+        cw = R.geo_uniform ? flux_face<D, true>(R, i, j, k, which) : flux_face<D, false>(R, i, j, k, which);
     }
     if (!do_cfl) return;
     __shared__ double red[4];
@@ -345,18 +358,13 @@ __device__ __forceinline__ void source_terms(const St& s, const double* __restri
     S[3] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
-                                                int nruns, int stage) {
-    const int r = find_run(boff, nruns, blockIdx.x);
-    const RunDev& R = runs[r];
-    if (!R.var->active) return;
-    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
-    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)n1 * n2 * n3) return;
-    const int k = (int)(e % n3);
-    const int64_t t = e / n3;
-    const int j = (int)(t % n2);
-    const int i = (int)(t / n2);
+// Conserved state after the stage update of interior cell (i,j,k): flux-CT, the flux divergence,
+// the centred source from the stage-input primitives Pg, U = U(P^n) + c dt L.  With ENT = false
+// the entropy component (used only by the entropy inversion) is skipped.
+template <bool ENT, bool UNI>
+__device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k, int stage, double* U, double* Pg,
+                                            Geo& G, St& sg, int64_t& gi_out) {
+    const int n2 = R.n2, n3 = R.n3;
     const int64_t ci = cell_index(R, i, j, k);
     const int64_t vs = R.vs, s1 = R.s1, s2 = R.s2;
     const int64_t kb = ci - k;
@@ -366,17 +374,17 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
     const double* __restrict__ F2 = R.F[2];
     const double* __restrict__ F3 = R.F[3];
     const bool has3 = R.act1 && R.act2, has1 = R.act2 && R.act3, has2 = R.act1 && R.act3;
+    constexpr int NQ = ENT ? NCS : 8;
 
     // ---- L = -sum_d (F_d(+) - F_d(-)) / dX^d with flux-CT for the field components ----
     double L[NCS];
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) L[q] = 0.0;
     {
         const int64_t cp = ci + s1;
-        // non-field components
-#pragma unroll
-        for (int q = 0; q < NCS; ++q) L[q] = 0.0;
         if (R.act1) {
 #pragma unroll
-            for (int q = 0; q < NCS; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 if (q >= 5 && q <= 7) continue;
                 L[q] -= (F1[q * vs + cp] - F1[q * vs + ci]) * R.idx[1];
             }
@@ -384,14 +392,14 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
         if (R.act2) {
             const int64_t cq = ci + s2;
 #pragma unroll
-            for (int q = 0; q < NCS; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 if (q >= 5 && q <= 7) continue;
                 L[q] -= (F2[q * vs + cq] - F2[q * vs + ci]) * R.idx[2];
             }
         }
         if (R.act3) {
 #pragma unroll
-            for (int q = 0; q < NCS; ++q) {
+            for (int q = 0; q < NQ; ++q) {
                 if (q >= 5 && q <= 7) continue;
                 L[q] -= (F3[q * vs + ckp] - F3[q * vs + ci]) * R.idx[3];
             }
@@ -483,53 +491,142 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
         }
     }
 
-    const int64_t gi = geo_index(R, i, j);
-    Geo G;
+    int64_t gi = geo_index(R, i, j);
+    if (UNI) gi = __builtin_amdgcn_readfirstlane((int)gi);
+    gi_out = gi;
     load_geo(R.gc, R.gpts, gi, G);
     const double gam = R.gam;
-    double* __restrict__ Pn = R.P;
+    const double* __restrict__ Pn = R.P;
     const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
-    double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
-
-    double U[NCS];
     {
         double P0[NPR];
 #pragma unroll
         for (int q = 0; q < NPR; ++q) P0[q] = Pn[q * vs + ci];
         St s0;
         prim_state(P0, G, gam, s0);
-        flux_of<0>(P0, s0, G, s0.p * pow(P0[0], 1.0 - gam), U);
+        flux_of<0>(P0, s0, G, ENT ? s0.p * pow(P0[0], 1.0 - gam) : 0.0, U);
     }
-    double Pg[NPR];
 #pragma unroll
     for (int q = 0; q < NPR; ++q) Pg[q] = Pin[q * vs + ci];
-    {
-        St sg;
-        prim_state(Pg, G, gam, sg);
-        double S[4];
-        source_terms(sg, R.gc, R.gpts, gi, G, S);
-        L[1] += S[0];
-        L[2] += S[1];
-        L[3] += S[2];
-        L[4] += S[3];
-    }
+    prim_state(Pg, G, gam, sg);
+    double S[4];
+    source_terms(sg, R.gc, R.gpts, gi, G, S);
+    L[1] += S[0];
+    L[2] += S[1];
+    L[3] += S[2];
+    L[4] += S[3];
     const double h = (stage == 1 ? 0.5 : 1.0) * R.var->dt;
 #pragma unroll
     for (int q = 0; q < NCS; ++q) U[q] += h * L[q];
+}
 
+// Fast path of the inversion: Newton-Raphson accepted when converged and physical, floors, and
+// the Lorentz cap.  Cells that need the entropy method (beta switch), Brent, or a magnetisation
+// ceiling go to the run's slow list and are finished by k_update_slow with the full procedure.
+template <bool UNI>
+__device__ __forceinline__ void update_fast(const RunDev& R, int stage, int64_t e) {
+    const int n2 = R.n2, n3 = R.n3;
+    const int k = (int)(e % n3);
+    const int64_t t = e / n3;
+    const int j = (int)(t % n2);
+    const int i = (int)(t / n2);
+    double U[NCS], Pg[NPR];
+    Geo G;
+    St sg;
+    int64_t gi;
+    stage_state<false, UNI>(R, i, j, k, stage, U, Pg, G, sg, gi);
+    bool slow = sg.p < R.beta_ent * 0.5 * sg.bsq;
     double P[NPR];
-#pragma unroll
-    for (int q = 0; q < NPR; ++q) P[q] = Pg[q];
-    const int m = invert_cell(U, Pg, G, R, P);
-    if (m >= 0) {
-        apply_floors(R, G, R.gc[G_RHOFL * R.gpts + gi], R.gc[G_UFL * R.gpts + gi], P);
-    } else {
-        const int pos = atomicAdd(&R.var->fail_count, 1);
-        R.fail_list[pos] = (int)e;
+    if (!slow) {
+        Inv q;
+        inv_setup(U, G, R.gam, q);
+        double W = sg.lor * sg.lor * sg.w;
+        const double qsq = sg.lor * sg.lor - 1.0;
+        double v2 = qsq / (1.0 + qsq);
+        slow = !newton2d(q, R.c2p_tol, R.c2p_maxit, W, v2);
+        if (!slow) {
+            const double rho = q.D * sqrt(1.0 - v2);
+            const double p = p_of_w(q, W, v2);
+            slow = !is_physical(W, v2, rho, p);
+            if (!slow) {
+                P[0] = rho;
+                P[1] = p / (q.gam - 1.0);
+                velocity_out(q, G, W, v2, P);
+                const double ig = 1.0 / G.gdet;
+                P[5] = U[5] * ig;
+                P[6] = U[6] * ig;
+                P[7] = U[7] * ig;
+                P[0] = fmax(P[0], R.gc[G_RHOFL * R.gpts + gi]);
+                P[1] = fmax(P[1], R.gc[G_UFL * R.gpts + gi]);
+                St s;
+                prim_state(P, G, R.gam, s);
+                slow = (s.bsq / R.bsq_rho_max - P[0] > 0.0) || (s.bsq / R.bsq_u_max - P[1] > 0.0);
+                if (!slow && s.lor > R.gamma_max) {
+                    const double f = sqrt((R.gamma_max * R.gamma_max - 1.0) / (s.lor * s.lor - 1.0));
+                    P[2] *= f;
+                    P[3] *= f;
+                    P[4] *= f;
+                }
+            }
+        }
     }
-    R.code[ci] = (int8_t)m;
+    if (slow) {
+        const int pos = atomicAdd(&R.var->slow_count, 1);
+        R.slow_list[pos] = (int)e;
+        return;
+    }
+    const int64_t ci = cell_index(R, i, j, k);
+    double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
+    R.code[ci] = 0;
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = P[q];
+    for (int q = 0; q < NPR; ++q) Pout[q * R.vs + ci] = P[q];
+}
+
+__global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
+                                                int nruns, int stage) {
+    const int r = find_run(boff, nruns, blockIdx.x);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)R.n1 * R.n2 * R.n3) return;
+    if (R.geo_uniform) update_fast<true>(R, stage, e);
+    else update_fast<false>(R, stage, e);
+}
+
+// Slow path: the full inversion (beta switch, NR, Brent on W, entropy) and the full floors with
+// ceilings, for the cells the fast path listed.  SLOWB workgroups per run stride over the list.
+constexpr int SLOWB = 64;
+
+__global__ __launch_bounds__(256) void k_update_slow(const RunDev* __restrict__ runs, int nruns, int stage) {
+    const int r = blockIdx.x / SLOWB;
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n = R.var->slow_count;
+    const int n2 = R.n2, n3 = R.n3;
+    for (int x = (blockIdx.x % SLOWB) * blockDim.x + threadIdx.x; x < n; x += SLOWB * blockDim.x) {
+        const int e = R.slow_list[x];
+        const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+        double U[NCS], Pg[NPR];
+        Geo G;
+        St sg;
+        int64_t gi;
+        stage_state<true, false>(R, i, j, k, stage, U, Pg, G, sg, gi);
+        double P[NPR];
+#pragma unroll
+        for (int q = 0; q < NPR; ++q) P[q] = Pg[q];
+        const int m = invert_cell(U, Pg, G, R, P);
+        if (m >= 0) {
+            apply_floors(R, G, R.gc[G_RHOFL * R.gpts + gi], R.gc[G_UFL * R.gpts + gi], P);
+        } else {
+            const int pos = atomicAdd(&R.var->fail_count, 1);
+            R.fail_list[pos] = e;
+        }
+        const int64_t ci = cell_index(R, i, j, k);
+        double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
+        R.code[ci] = (int8_t)m;
+#pragma unroll
+        for (int q = 0; q < NPR; ++q) Pout[q * R.vs + ci] = P[q];
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -639,6 +736,7 @@ __global__ __launch_bounds__(256) void k_fixup(const RunDev* __restrict__ runs, 
     }
     if (threadIdx.x == 0) {
         V->fail_count = 0;
+        V->slow_count = 0;
         if (stage == 2) V->active = V->steps_left > 0 ? 1 : 0;
     }
 }
@@ -786,6 +884,10 @@ void launch_dt(const RunDev* runs, int nruns, hipStream_t st) {
 
 void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st) {
     if (nblocks > 0) k_update<<<nblocks, 256, 0, st>>>(runs, boff, nruns, stage);
+}
+
+void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st) {
+    k_update_slow<<<nruns * SLOWB, 256, 0, st>>>(runs, nruns, stage);
 }
 
 void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st) {

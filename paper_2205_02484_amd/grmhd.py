@@ -240,7 +240,7 @@ class Context:
         _check(load().grmhd_diag(self._h, ctypes.byref(m), ctypes.byref(f)))
         return m.value, f.value
 
-    KERNELS = ("bound", "flux1", "flux2", "flux3", "dt", "update", "fixup")
+    KERNELS = ("bound", "flux1", "flux2", "flux3", "dt", "update", "fixup", "update_slow")
 
     def kernel_timing(self, on: bool):
         _check(load().grmhd_kernel_timing(self._h, int(bool(on))))

@@ -51,3 +51,20 @@ def scaled_abs_err(x, y):
     d = np.abs(x - y).reshape(nv, -1).max(axis=1)
     with np.errstate(invalid="ignore", divide="ignore"):
         return float(np.where(sc > 0, d / np.where(sc > 0, sc, 1.0), np.where(d == 0, 0.0, np.inf)).max())
+
+
+NAMES = ("rho", "u", "u~1", "u~2", "u~3", "B1", "B2", "B3")
+
+
+def worst(x, y):
+    """Description of the worst cell under rel_err (for assertion messages)."""
+    e = rel_err(x, y)
+    idx = np.unravel_index(int(np.argmax(e)), e.shape)
+    var = NAMES[idx[0]] if y.shape[0] == 8 else str(idx[0])
+    return (f"err {e[idx]:.3e} at {var}{tuple(int(v) for v in idx[1:])}: gpu {x[idx]!r} oracle {y[idx]!r}; "
+            f"per-variable max {np.array2string(e.reshape(e.shape[0], -1).max(axis=1), precision=2)}")
+
+
+def assert_parity(x, y, tol):
+    err = max_rel_err(x, y)
+    assert err < tol, worst(x, y)
