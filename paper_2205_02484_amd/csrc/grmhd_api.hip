@@ -385,7 +385,7 @@ struct Engine {
             for (int d = 1; d <= 3; ++d) {
                 if (nblk[kf[d]] <= 0) continue;
                 mark(TK_FLUX1 + d - 1);
-                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, st);
+                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, 0, st);
                 mark(TK_FLUX1 + d - 1);
             }
             if (stage == 1) {
@@ -692,7 +692,7 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     const int kind = d == 1 ? KB_F1 : (d == 2 ? KB_F2 : KB_F3);
     HIPCHK(hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st));
     launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, st);
-    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, st);
+    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, st);
     const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
     double* dF = nullptr;
     HIPCHK(hipMalloc(&dF, n * 8));

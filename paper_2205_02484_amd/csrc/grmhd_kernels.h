@@ -15,8 +15,9 @@ struct GeoArgs {
 
 void launch_geometry(const GeoArgs& A, hipStream_t st);
 void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, hipStream_t st);
+// ent = 1 also computes and stores the entropy component (diagnostics); the stage chain uses 0
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 hipStream_t st);
+                 int ent, hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
 void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st);
 void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st);

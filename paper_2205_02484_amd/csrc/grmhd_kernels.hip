@@ -189,17 +189,23 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // One face: returns c_w (0 when the face does not count for the CFL step).  The left state's
-// conserved vector, flux and speeds are finished before the right state is formed, and the
-// right state's components are folded into the Riemann flux as they are produced, which keeps
-// the live register set to one state plus two 9-vectors.
-template <int D, bool UNI>
-__device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k, int which) {
+// conserved vector, flux and speeds are finished before the right state is formed, which keeps
+// the live register set to one state plus two flux vectors.  With ENT = false the entropy
+// component (read only by the entropy inversion of the slow path, which recomputes it for its
+// own faces) is neither computed nor stored: that saves both powers of rho per face.
+template <int D, bool UNI, bool ENT>
+__device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k, int which, double* ent_out) {
+    constexpr int NQ = ENT ? NCS : 8;
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
     const int64_t ci = cell_index(R, i, j, k);
     double* __restrict__ F = R.F[D];
     if (D == 2 && R.mks && (j == 0 || j == n2)) {
+        if (ent_out) {
+            *ent_out = 0.0;
+            return 0.0;
+        }
 #pragma unroll
-        for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.0;
+        for (int q = 0; q < NQ; ++q) F[q * R.vs + ci] = 0.0;
         return 0.0;
     }
     const double* __restrict__ P = which ? R.Ph : R.P;
@@ -230,14 +236,14 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
     {
         St s;
         prim_state(Pl, G, gam, s);
-        const double ent = s.p * pow(Pl[0], 1.0 - gam);
+        const double ent = ENT ? s.p * pow(Pl[0], 1.0 - gam) : 0.0;
         wave_speeds<D>(s, G, gam, c1l, c2l);
         flux_of<0>(Pl, s, G, ent, Ul);
         flux_of<D>(Pl, s, G, ent, Fl);
     }
     St s;
     prim_state(Pr, G, gam, s);
-    const double entr = s.p * pow(Pr[0], 1.0 - gam);
+    const double entr = ENT ? s.p * pow(Pr[0], 1.0 - gam) : 0.0;
     double c1r, c2r;
     wave_speeds<D>(s, G, gam, c1r, c2r);
     const double cmax = fmax(0.0, fmax(c1r, c1l));
@@ -246,23 +252,38 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
     double Ur[NCS], Fr[NCS];
     flux_of<0>(Pr, s, G, entr, Ur);
     flux_of<D>(Pr, s, G, entr, Fr);
+    double out[NCS];
     if (R.riemann == 1) {
         const double den = cmax + cmin;
         const double id = den > 0.0 ? 1.0 / den : 0.0;
 #pragma unroll
-        for (int q = 0; q < NCS; ++q)
-            F[q * R.vs + ci] = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
-                                         : 0.5 * (Fl[q] + Fr[q]);
+        for (int q = 0; q < NQ; ++q)
+            out[q] = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
+                               : 0.5 * (Fl[q] + Fr[q]);
     } else {
 #pragma unroll
-        for (int q = 0; q < NCS; ++q) F[q * R.vs + ci] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
+        for (int q = 0; q < NQ; ++q) out[q] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
     }
+    if (ent_out) {
+        *ent_out = out[NCS - 1];
+        return 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) F[q * R.vs + ci] = out[q];
     if (D != 1 && (i < 0 || i >= n1)) return 0.0;
     if (D != 2 && (j < 0 || j >= n2)) return 0.0;
     return cwf;
 }
 
+// Entropy component of the Riemann flux through face (i,j,k) along D, recomputed on demand.
 template <int D>
+__device__ __forceinline__ double entropy_flux(const RunDev& R, int i, int j, int k, int which) {
+    double f = 0.0;
+    flux_face<D, false, true>(R, i, j, k, which, &f);
+    return f;
+}
+
+template <int D, bool ENT>
 __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                               int nruns, int which, int do_cfl) {
     const int r = find_run(boff, nruns, blockIdx.x);
@@ -281,7 +302,9 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
         const int64_t t = e / n3;
         const int j = (int)(t % nj) + j0;
         const int i = (int)(t / nj) + i0;
-        cw = R.geo_uniform ? flux_face<D, true>(R, i, j, k, which) : flux_face<D, false>(R, i, j, k, which);
+        if (ENT) cw = flux_face<D, false, true>(R, i, j, k, which, nullptr);
+        else if (R.geo_uniform) cw = flux_face<D, true, false>(R, i, j, k, which, nullptr);
+        else cw = flux_face<D, false, false>(R, i, j, k, which, nullptr);
     }
     if (!do_cfl) return;
     __shared__ double red[4];
@@ -374,12 +397,21 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const double* __restrict__ F2 = R.F[2];
     const double* __restrict__ F3 = R.F[3];
     const bool has3 = R.act1 && R.act2, has1 = R.act2 && R.act3, has2 = R.act1 && R.act3;
-    constexpr int NQ = ENT ? NCS : 8;
+    constexpr int NQ = 8;   // the stored flux arrays carry no entropy component
 
     // ---- L = -sum_d (F_d(+) - F_d(-)) / dX^d with flux-CT for the field components ----
     double L[NCS];
 #pragma unroll
     for (int q = 0; q < NCS; ++q) L[q] = 0.0;
+    if (ENT) {
+        const int which = stage - 1;
+        if (R.act1) L[8] -= (entropy_flux<1>(R, i + 1, j, k, which) - entropy_flux<1>(R, i, j, k, which)) * R.idx[1];
+        if (R.act2) L[8] -= (entropy_flux<2>(R, i, j + 1, k, which) - entropy_flux<2>(R, i, j, k, which)) * R.idx[2];
+        if (R.act3) {
+            const int kp = k + 1 == n3 ? 0 : k + 1;
+            L[8] -= (entropy_flux<3>(R, i, j, kp, which) - entropy_flux<3>(R, i, j, k, which)) * R.idx[3];
+        }
+    }
     {
         const int64_t cp = ci + s1;
         if (R.act1) {
@@ -871,11 +903,17 @@ void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, i
 }
 
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 hipStream_t st) {
+                 int ent, hipStream_t st) {
     if (nblocks <= 0) return;
-    if (d == 1) k_flux<1><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
-    else if (d == 2) k_flux<2><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
-    else k_flux<3><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+    if (ent) {
+        if (d == 1) k_flux<1, true><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+        else if (d == 2) k_flux<2, true><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+        else k_flux<3, true><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+    } else {
+        if (d == 1) k_flux<1, false><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+        else if (d == 2) k_flux<2, false><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+        else k_flux<3, false><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+    }
 }
 
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st) {

@@ -4,13 +4,16 @@ For primitive states P = (rho, u, u~1, u~2, u~3, B1, B2, B3):
 
     err = |x - y| / max(|y|, 1e-3 * S_k)      (0 where x == y)
 
-with S_k the scale of variable k over all cells: max|rho| for rho, max|u| for u, the largest
-component of the field for every B^i (the three components are one vector), and for every u~^i
-the largest velocity component but at least 1 (u~ is a spatial 4-velocity in units of c, so an
-absolute difference of a few ulp of 1 is the rounding limit however slow the local flow is).
-Relative where a quantity is not tiny against its own scale, absolute at 1e-3 of that scale
-otherwise: floors and the atmosphere hold values many decades below the torus, where the
-inversion is ill-conditioned and no FP64 implementation can fix more digits.
+with S_k the scale of variable k: max|rho| over all cells for rho; for u, the larger of max|u|
+over all cells and the local rest-mass energy density rho of the cell (u is recovered from the
+energy equation as the difference between the total energy and the rest mass, so its absolute
+precision is a few ulp of rho whatever the implementation: in the cold inner edge of a torus,
+u/rho ~ 3e-4, that alone is ~1e-12 of u); the largest component of the field for every B^i (the
+three components are one vector); and for every u~^i the largest velocity component but at least
+1 (u~ is a spatial 4-velocity in units of c, so a few ulp of 1 is the rounding limit however
+slow the local flow is).  Relative where a quantity is not tiny against its own scale, absolute
+at 1e-3 of that scale otherwise: floors and the atmosphere hold values many decades below the
+torus, where the inversion is ill-conditioned and no FP64 implementation can fix more digits.
 
 For conserved vectors and fluxes each of the 9 components is its own scale."""
 import numpy as np
@@ -31,6 +34,8 @@ def rel_err(x, y):
     nv = y.shape[0]
     sc = _scales(y)
     den = np.maximum(np.abs(y), 1e-3 * sc.reshape((nv,) + (1,) * (y.ndim - 1)))
+    if nv == 8:
+        den[1] = np.maximum(den[1], 1e-3 * np.abs(y[0]))
     with np.errstate(invalid="ignore", divide="ignore"):
         e = np.where(den > 0, np.abs(x - y) / np.where(den > 0, den, 1.0), np.where(x == y, 0.0, np.inf))
     return e
