@@ -19,10 +19,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # algorithmic HBM bytes per unit processed by each kernel (state/flux traffic, FP64)
-#   flux_d : per face, the primitives of one cell (8 x 8 B) + the 9-component flux written (72 B)
-#   update : per cell, three face fluxes (3 x 72 B), P^n and the stage input (2 x 64 B), P_out (64 B),
+#   flux_d : per face, the primitives of one cell (8 x 8 B) + the 8-component flux written (64 B)
+#   update : per cell, three face fluxes (3 x 64 B), P^n and the stage input (2 x 64 B), P_out (64 B),
 #            method code (1 B)
-ALG_BYTES = {"flux1": 136.0, "flux2": 136.0, "flux3": 136.0, "update": 409.0, "bound": 128.0}
+#   bound  : per ghost cell, 8 primitives read and written
+ALG_BYTES = {"flux1": 128.0, "flux2": 128.0, "flux3": 128.0, "update": 385.0, "bound": 128.0}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -55,6 +56,40 @@ def cpu_baseline(cfg, P, nsteps):
                       f"{el:.1f} s wall"}
 
 
+def ensemble_legs(args, stream):
+    """48 uneven tori batched vs one after another, then a served Poisson stream at 80 % of the
+    batched capacity with continuous admission; p50/p99 job latency (arrival -> done)."""
+    from paper_2205_02484_amd import serve
+    jobs = serve.ensemble_jobs(seed=4, nsteps=args.ensemble_steps)
+    from paper_2205_02484_amd.torus_init import make_torus
+    inputs = [make_torus(j.cfg) for j in jobs]
+    print(f"[bench] ensemble: {len(jobs)} tori x {args.ensemble_steps} steps, batched", file=sys.stderr, flush=True)
+    bat = serve.run_batched(jobs, steps_per_launch=25, stream=stream, inputs=inputs)
+    print(f"[bench] ensemble batched {bat['zu_per_s']:.3e} ZU/s; sequential", file=sys.stderr, flush=True)
+    seq = serve.run_sequential(jobs, stream=stream, inputs=inputs)
+    print(f"[bench] ensemble sequential {seq['zu_per_s']:.3e} ZU/s", file=sys.stderr, flush=True)
+    rate = 0.8 * bat["zu_per_s"] / serve.mean_job_zone_updates(seed=5)
+    sjobs = serve.served_jobs(rate_hz=rate, duration_s=args.serve_seconds, seed=5)
+    print(f"[bench] served stream: {len(sjobs)} jobs over {args.serve_seconds:.0f} s at {rate:.3f}/s",
+          file=sys.stderr, flush=True)
+    srv = serve.serve(sjobs, steps_per_launch=20, stream=stream,
+                      log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(f"[bench] served p50 {srv['p50_s']:.2f} s p99 {srv['p99_s']:.2f} s, {srv['zu_per_s']:.3e} ZU/s",
+          file=sys.stderr, flush=True)
+    return {
+        "workload": "48 seeded tori (24 2D 64^2-192^2, 24 3D 48-96 x 48 x 48), spin U[0,0.98], "
+                    "gamma {4/3,13/9,5/3}, beta {30,100,300}, r_max U[10,30]",
+        "steps_each": args.ensemble_steps,
+        "batched_zu_per_s": bat["zu_per_s"], "batched_seconds": bat["seconds"],
+        "sequential_zu_per_s": seq["zu_per_s"], "sequential_seconds": seq["seconds"],
+        "batched_over_sequential": bat["zu_per_s"] / seq["zu_per_s"],
+        "served": {"duration_s": args.serve_seconds, "rate_hz": rate, "load": 0.8, "jobs": srv["jobs"],
+                   "p50_s": srv["p50_s"], "p99_s": srv["p99_s"], "mean_s": srv["mean_s"],
+                   "zu_per_s": srv["zu_per_s"], "seconds": srv["seconds"],
+                   "mix": "2D 128^2 or 3D N^3 (N in [64,160]), 100-2000 steps each"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +98,12 @@ def main():
     ap.add_argument("--workload", default="torus3d_256x256x256")
     ap.add_argument("--cpu-steps", type=int, default=1, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble and served-stream legs")
+    ap.add_argument("--ensemble-steps", type=int, default=500, help="steps of each of the 48 ensemble tori")
+    ap.add_argument("--serve-seconds", type=float, default=30.0, help="length of the served arrival stream")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size kernel that "
+                         "scales the HBM counters of a profiler pass)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
@@ -79,6 +120,15 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     grmhd.load()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     cfg = WORKLOADS[args.workload]()
     P = make_torus(cfg)
     n1, n2, n3 = cfg.n1, cfg.n2, cfg.n3
@@ -118,7 +168,7 @@ def main():
                for k, v in kt.items()}
 
     out = {
-        "metric": "FP64 zone-updates/s (256^3 torus)",
+        "metric": "FP64 zone-updates/s (256^3 torus) + ensemble p50/p99 latency vs plain",
         "value": value,
         "unit": "zone-updates/s",
         "n_gpus": 1,
@@ -141,6 +191,8 @@ def main():
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
+    if not args.no_ensemble:
+        out["ensemble"] = ensemble_legs(args, stream)
     if not args.no_cpu_baseline:
         print(f"[bench] CPU baseline: oracle, {args.cpu_steps} step(s)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, P, args.cpu_steps)

@@ -13,6 +13,15 @@
 
 namespace grmhd {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8), each
+// with its own L2.  Remapping so that every XCD walks a contiguous range of logical blocks keeps
+// the rows a stencil shares inside one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b & 7, m = b >> 3;
+    const int q = nb >> 3, rem = nb & 7;
+    return x * q + (x < rem ? x : rem) + m;
+}
+
 __device__ __forceinline__ int find_run(const int* __restrict__ boff, int nruns, int b) {
     int lo = 0, hi = nruns;
     while (hi - lo > 1) {
@@ -128,11 +137,12 @@ __global__ void k_geometry(GeoArgs A) {
 // ------------------------------------------------------------------------------------------
 
 __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns, int which) {
-    const int r = find_run(boff, nruns, blockIdx.x);
+    const int bl = xcd_block(blockIdx.x, gridDim.x);
+    const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
-    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
     const int ncolA = 4 * (n2 + 2 * NG);
     const int64_t total = (int64_t)(ncolA + 4 * n1) * n3;
     if (e >= total) return;
@@ -286,7 +296,8 @@ __device__ __forceinline__ double entropy_flux(const RunDev& R, int i, int j, in
 template <int D, bool ENT>
 __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                               int nruns, int which, int do_cfl) {
-    const int r = find_run(boff, nruns, blockIdx.x);
+    const int bl = xcd_block(blockIdx.x, gridDim.x);
+    const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
@@ -294,14 +305,22 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     const int j0 = D == 2 ? 0 : -R.act2;
     const int ni = D == 1 ? n1 + 1 : n1 + 2 * R.act1;
     const int nj = D == 2 ? n2 + 1 : n2 + 2 * R.act2;
-    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)ni * nj * n3;
     double cw = 0.0;
     if (e < total) {
+        // rows of n3 faces, ordered so that neighbouring rows along the stencil direction are
+        // consecutive (X1 faces: i fastest; X2 and X3 faces: j fastest)
         const int k = (int)(e % n3);
         const int64_t t = e / n3;
-        const int j = (int)(t % nj) + j0;
-        const int i = (int)(t / nj) + i0;
+        int i, j;
+        if (D == 1) {
+            i = (int)(t % ni) + i0;
+            j = (int)(t / ni) + j0;
+        } else {
+            j = (int)(t % nj) + j0;
+            i = (int)(t / nj) + i0;
+        }
         if (ENT) cw = flux_face<D, false, true>(R, i, j, k, which, nullptr);
         else if (R.geo_uniform) cw = flux_face<D, true, false>(R, i, j, k, which, nullptr);
         else cw = flux_face<D, false, false>(R, i, j, k, which, nullptr);
@@ -616,10 +635,11 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int stage, int64_t 
 
 __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                                 int nruns, int stage) {
-    const int r = find_run(boff, nruns, blockIdx.x);
+    const int bl = xcd_block(blockIdx.x, gridDim.x);
+    const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
-    const int64_t e = (int64_t)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
     if (e >= (int64_t)R.n1 * R.n2 * R.n3) return;
     if (R.geo_uniform) update_fast<true>(R, stage, e);
     else update_fast<false>(R, stage, e);

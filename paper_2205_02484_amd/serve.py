@@ -1,0 +1,223 @@
+"""Ensemble stepping and a continuously-batched request loop over the C ABI's grmhd_batch_*.
+
+Jobs are torus runs of different grids, spins, adiabatic indices and field strengths -- the kind
+of parameter scan the paper runs over beta_0, disk size and gamma (Sec. 5, Table 1).  Each admitted
+job's state stays resident in HBM; all active jobs advance together (one launch per stage kernel
+for the whole ensemble, each job with its own CFL step) until they have taken their requested
+number of steps.  New jobs are admitted whenever their memory footprint fits, while others run.
+
+This module only orchestrates: every step of the method runs in libgrmhd.so.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from . import grmhd
+from .torus_init import TorusConfig, fm_torus_2d, make_torus
+
+
+@dataclasses.dataclass
+class Job:
+    jid: int
+    cfg: TorusConfig
+    nsteps: int
+    arrival: float = 0.0          # seconds after the stream starts
+    admitted: Optional[float] = None
+    done: Optional[float] = None
+    handle: Optional[int] = None
+
+    @property
+    def zone_updates(self) -> int:
+        return self.cfg.zones * self.nsteps
+
+
+def _torus_exists(cfg: TorusConfig) -> bool:
+    ii, jj = np.meshgrid(np.arange(cfg.n1), np.arange(cfg.n2), indexing="ij")
+    return bool(fm_torus_2d(cfg, ii, jj)[4].any())
+
+
+def _random_physics(rng, n1, n2, n3, seed) -> TorusConfig:
+    """Spin U[0, 0.98], gamma in {4/3, 13/9, 5/3}, beta_0 in {30, 100, 300}, r_max U[10, 30],
+    r_in = r_max/2 (moved out by 0.5 M until a torus exists on the grid), r_out = 1000."""
+    spin = float(rng.uniform(0.0, 0.98))
+    gam = float(rng.choice([4.0 / 3.0, 13.0 / 9.0, 5.0 / 3.0]))
+    beta = float(rng.choice([30.0, 100.0, 300.0]))
+    r_max = float(rng.uniform(10.0, 30.0))
+    r_in = r_max / 2.0
+    cfg = None
+    while r_in < r_max:
+        cfg = TorusConfig(n1=n1, n2=n2, n3=n3, spin=spin, gam=gam, beta=beta, r_max=r_max, r_in=r_in,
+                          r_out=1000.0, delta=0.04, seed=seed, cfl=0.45)
+        if _torus_exists(cfg):
+            return cfg
+        r_in += 0.5
+    raise RuntimeError("no torus for this draw")
+
+
+def ensemble_jobs(seed: int = 4, n2d: int = 24, n3d: int = 24, nsteps: int = 500) -> List[Job]:
+    """The uneven 48-torus ensemble: half 2D N x N with N in {64..192}, half 3D N1 x 48 x 48 with
+    N1 in {48..96}, physics drawn as in _random_physics."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for x in range(n2d + n3d):
+        if x < n2d:
+            n = int(rng.integers(64, 193))
+            cfg = _random_physics(rng, n, n, 1, seed * 1000 + x)
+        else:
+            n1 = int(rng.integers(48, 97))
+            cfg = _random_physics(rng, n1, 48, 48, seed * 1000 + x)
+        jobs.append(Job(jid=x, cfg=cfg, nsteps=nsteps))
+    return jobs
+
+
+def served_jobs(rate_hz: float, duration_s: float, seed: int = 5) -> List[Job]:
+    """Poisson arrivals over `duration_s`: 2D 128^2 or 3D N^3 (N in [64, 160]) tori requesting
+    100..2000 steps, physics as in _random_physics."""
+    rng = np.random.default_rng(seed)
+    jobs, t, x = [], 0.0, 0
+    while True:
+        t += float(rng.exponential(1.0 / rate_hz))
+        if t >= duration_s:
+            break
+        if rng.random() < 0.5:
+            cfg = _random_physics(rng, 128, 128, 1, seed * 100000 + x)
+        else:
+            n = int(rng.integers(64, 161))
+            cfg = _random_physics(rng, n, n, n, seed * 100000 + x)
+        jobs.append(Job(jid=x, cfg=cfg, nsteps=int(rng.integers(100, 2001)), arrival=t))
+        x += 1
+    return jobs
+
+
+def mean_job_zone_updates(seed: int = 5, samples: int = 4000) -> float:
+    """E[zones x steps] of the served job mix (sizes and step counts only)."""
+    rng = np.random.default_rng(seed + 12345)
+    tot = 0.0
+    for _ in range(samples):
+        if rng.random() < 0.5:
+            z = 128 * 128
+        else:
+            z = int(rng.integers(64, 161)) ** 3
+        tot += z * float(rng.integers(100, 2001))
+    return tot / samples
+
+
+def run_sequential(jobs: List[Job], stream=None, inputs: Optional[List[np.ndarray]] = None) -> Dict[str, float]:
+    """Each job alone with the plain stepper (one context at a time)."""
+    import torch
+    if inputs is None:
+        inputs = [make_torus(j.cfg) for j in jobs]
+    t0 = time.perf_counter()
+    zu = 0
+    for j, P in zip(jobs, inputs):
+        ctx = grmhd.Context(j.cfg, P, stream=stream)
+        ctx.steps(j.nsteps)
+        ctx.get_time()                       # waits for the run
+        ctx.close()
+        zu += j.zone_updates
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el}
+
+
+def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
+                keep: Optional[Callable[[Job, np.ndarray], None]] = None,
+                inputs: Optional[List[np.ndarray]] = None) -> Dict[str, float]:
+    """All jobs resident together, advanced in one kernel chain until each is done."""
+    b = grmhd.Batch(stream=stream)
+    if inputs is None:
+        inputs = [make_torus(j.cfg) for j in jobs]
+    t0 = time.perf_counter()
+    by_handle = {}
+    for j, P in zip(jobs, inputs):
+        h = b.admit(j.cfg, P, j.nsteps)
+        if h is None:
+            raise RuntimeError("ensemble does not fit the device memory budget")
+        j.handle = h
+        by_handle[h] = j
+    left = len(jobs)
+    zu = 0
+    while left:
+        b.advance(steps_per_launch)
+        for h in b.poll():
+            j = by_handle[h]
+            if keep is not None:
+                keep(j, b.fetch(h)[0])
+            b.release(h)
+            zu += j.zone_updates
+            left -= 1
+    el = time.perf_counter() - t0
+    b.close()
+    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el}
+
+
+def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, stream=None,
+          log: Optional[Callable[[str], None]] = None, batch=None,
+          make_input: Callable[[TorusConfig], np.ndarray] = make_torus,
+          clock: Callable[[], float] = time.perf_counter,
+          sleep: Callable[[float], None] = time.sleep) -> Dict[str, float]:
+    """Replay an arrival stream in real time with continuous batching.
+
+    Arrived jobs wait in a FIFO queue; every pass admits, in order, each queued job whose
+    footprint fits the remaining budget (smaller jobs may pass a large head), advances all active
+    jobs by `steps_per_launch` steps, and retires finished ones (fetch + release).  Latency is
+    arrival -> finished on the host.  `batch`, `make_input`, `clock` and `sleep` can be replaced
+    (host-side tests of the scheduling logic)."""
+    b = batch if batch is not None else grmhd.Batch(budget_bytes=budget_bytes, stream=stream)
+    time_now = clock
+    pending = sorted(jobs, key=lambda j: j.arrival)
+    inputs: Dict[int, np.ndarray] = {}
+    queue: List[Job] = []
+    active: Dict[int, Job] = {}
+    finished: List[Job] = []
+    t0 = time_now()
+    nxt = 0
+    zu = 0
+    last_log = t0
+    while nxt < len(pending) or queue or active:
+        now = time_now() - t0
+        while nxt < len(pending) and pending[nxt].arrival <= now:
+            j = pending[nxt]
+            inputs[j.jid] = make_input(j.cfg)
+            queue.append(j)
+            nxt += 1
+        still = []
+        for j in queue:
+            h = b.admit(j.cfg, inputs[j.jid], j.nsteps)
+            if h is None:
+                still.append(j)
+                continue
+            j.handle = h
+            j.admitted = time_now() - t0
+            active[h] = j
+            del inputs[j.jid]
+        queue = still
+        if active:
+            b.advance(steps_per_launch)
+            for h in b.poll():
+                j = active.pop(h)
+                b.fetch(h)
+                b.release(h)
+                j.done = time_now() - t0
+                zu += j.zone_updates
+                finished.append(j)
+        elif nxt < len(pending):
+            sleep(max(0.0, min(0.05, pending[nxt].arrival - (time_now() - t0))))
+        elif queue:
+            raise RuntimeError(f"job {queue[0].jid} can never fit the memory budget")
+        if log is not None and time_now() - last_log > 30.0:
+            last_log = time_now()
+            log(f"[serve] t={last_log - t0:.0f}s done={len(finished)} active={len(active)} queued={len(queue)}")
+    el = time_now() - t0
+    if batch is None:
+        b.close()
+    lat = np.array([j.done - j.arrival for j in finished])
+    return {"jobs": len(finished), "seconds": el, "zone_updates": zu, "zu_per_s": zu / el,
+            "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
+            "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+            "mean_s": float(lat.mean()) if len(lat) else math.nan}

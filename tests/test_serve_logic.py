@@ -1,0 +1,105 @@
+"""Host-side tests of the ensemble request loop's scheduling (no GPU): FIFO admission with
+backfill by memory footprint, every job retired exactly once, latency = done - arrival, and the
+seeded job streams."""
+import numpy as np
+
+from paper_2205_02484_amd import serve
+from paper_2205_02484_amd.torus_init import TorusConfig
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-3)
+
+
+class FakeBatch:
+    """Stands in for grmhd.Batch: footprint = zones bytes, a job finishes after nsteps steps,
+    each advanced step costs 1 ms of the fake clock."""
+
+    def __init__(self, budget, clock):
+        self.budget, self.used, self.clock = budget, 0, clock
+        self.jobs = {}
+        self.next = 1
+        self.admitted_order = []
+
+    def admit(self, cfg, P, nsteps):
+        need = cfg.zones
+        if self.used + need > self.budget:
+            return None
+        h = self.next
+        self.next += 1
+        self.jobs[h] = [need, nsteps, False]
+        self.used += need
+        self.admitted_order.append(cfg.seed)
+        return h
+
+    def advance(self, steps):
+        self.clock.t += 1e-3 * steps
+        for v in self.jobs.values():
+            v[1] -= steps
+
+    def poll(self):
+        out = []
+        for h, v in self.jobs.items():
+            if v[1] <= 0 and not v[2]:
+                v[2] = True
+                out.append(h)
+        return out
+
+    def fetch(self, h):
+        return None
+
+    def release(self, h):
+        self.used -= self.jobs.pop(h)[0]
+
+
+def _job(jid, n, steps, arrival):
+    return serve.Job(jid=jid, cfg=TorusConfig(n1=n, n2=n, n3=1, seed=jid), nsteps=steps, arrival=arrival)
+
+
+def test_all_jobs_finish_once_and_latency_is_done_minus_arrival():
+    clock = FakeClock()
+    fb = FakeBatch(budget=3 * 64 * 64, clock=clock)
+    jobs = [_job(i, 64, 30 + 10 * i, arrival=0.01 * i) for i in range(8)]
+    res = serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
+                      sleep=clock.sleep)
+    assert res["jobs"] == 8 and fb.used == 0
+    assert all(j.done is not None and j.done >= j.arrival for j in jobs)
+    lat = sorted(j.done - j.arrival for j in jobs)
+    assert res["p50_s"] == np.percentile(lat, 50)
+
+
+def test_memory_budget_is_never_exceeded_and_small_jobs_backfill():
+    clock = FakeClock()
+    fb = FakeBatch(budget=100 * 100, clock=clock)
+    seen_max = []
+    orig = fb.admit
+
+    def admit(cfg, P, n):
+        h = orig(cfg, P, n)
+        seen_max.append(fb.used)
+        return h
+    fb.admit = admit
+    jobs = [_job(0, 90, 100, 0.0), _job(1, 80, 50, 0.0), _job(2, 20, 20, 0.0)]
+    serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
+                sleep=clock.sleep)
+    assert max(seen_max) <= 100 * 100
+    # the 80^2 job does not fit beside the 90^2 one, the 20^2 job does and is admitted before it
+    assert fb.admitted_order.index(2) < fb.admitted_order.index(1)
+
+
+def test_ensemble_and_served_streams_are_seeded():
+    a = serve.ensemble_jobs(seed=4)
+    b = serve.ensemble_jobs(seed=4)
+    assert [(j.cfg.n1, j.cfg.n3, j.cfg.spin, j.cfg.gam) for j in a] == [(j.cfg.n1, j.cfg.n3, j.cfg.spin, j.cfg.gam) for j in b]
+    assert len(a) == 48 and sum(j.cfg.n3 == 1 for j in a) == 24
+    assert all(64 <= j.cfg.n1 <= 192 for j in a[:24]) and all(48 <= j.cfg.n1 <= 96 and j.cfg.n2 == 48 for j in a[24:])
+    s = serve.served_jobs(rate_hz=1.0, duration_s=30.0, seed=5)
+    assert all(100 <= j.nsteps <= 2000 for j in s)
+    assert all(x.arrival < y.arrival for x, y in zip(s, s[1:]))
