@@ -24,13 +24,13 @@ constexpr int NG = 2;   // ghost layers in X1 and X2
 enum {
     G_TT = 0, G_T1, G_T3, G_11, G_13, G_22, G_33,         // g_{mu nu}
     GI_TT, GI_T1, GI_11, GI_13, GI_22, GI_33,             // g^{mu nu}
-    G_DET, G_ALPHA,
-    G_D1 = 15,   // 1/2 sqrt(-g) d_1 g_{mu nu}, 7 entries in the order tt,t1,t3,11,13,22,33
-    G_D2 = 22,   // 1/2 sqrt(-g) d_2 g_{mu nu}
-    G_RHOFL = 29, G_UFL = 30,
-    NGC = 31
+    G_DET, G_ALPHA, G_IALPHA,                             // sqrt(-g), lapse, 1/lapse
+    G_D1,            // 1/2 sqrt(-g) d_1 g_{mu nu}, 7 entries in the order tt,t1,t3,11,13,22,33
+    G_D2 = G_D1 + 7, // 1/2 sqrt(-g) d_2 g_{mu nu}
+    G_RHOFL = G_D2 + 7, G_UFL,
+    NGC
 };
-constexpr int NGF = 15;  // faces carry the first 15 entries
+constexpr int NGF = G_IALPHA + 1;  // faces carry the entries up to 1/lapse
 
 // Per-run constant description (device copy, read with scalar loads).
 struct RunVar;
@@ -75,7 +75,7 @@ __device__ __forceinline__ int64_t geo_index(const RunDev& R, int i, int j) {
 struct Geo {
     double gtt, gt1, gt3, g11, g13, g22, g33;
     double Gtt, Gt1, G11, G13, G22, G33;
-    double gdet, alpha;
+    double gdet, alpha, ialpha;
 };
 
 __device__ __forceinline__ void load_geo(const double* __restrict__ g, int64_t np, int64_t gi, Geo& G) {
@@ -94,6 +94,7 @@ __device__ __forceinline__ void load_geo(const double* __restrict__ g, int64_t n
     G.G33 = g[GI_33 * np + gi];
     G.gdet = g[G_DET * np + gi];
     G.alpha = g[G_ALPHA * np + gi];
+    G.ialpha = g[G_IALPHA * np + gi];
 }
 
 // 4-velocity, field 4-vector and thermodynamics of one primitive state.
@@ -120,7 +121,7 @@ __device__ __forceinline__ void prim_state(const double* P, const Geo& G, double
     const double qsq = G.g11 * q1 * q1 + 2.0 * G.g13 * q1 * q3 + G.g22 * q2 * q2 + G.g33 * q3 * q3;
     const double lor = sqrt(1.0 + qsq);
     s.lor = lor;
-    s.ut = lor / G.alpha;
+    s.ut = lor * G.ialpha;
     s.u1 = q1 - lor * G.alpha * G.Gt1;
     s.u2 = q2;
     s.u3 = q3;

@@ -114,6 +114,7 @@ __global__ void k_geometry(GeoArgs A) {
         for (int n = 0; n < 6; ++n) out[(GI_TT + n) * (int64_t)np + e] = m.gi[n];
         out[G_DET * (int64_t)np + e] = m.gdet;
         out[G_ALPHA * (int64_t)np + e] = m.alpha;
+        out[G_IALPHA * (int64_t)np + e] = 1.0 / m.alpha;
         if (pass == 0) {
             for (int n = 0; n < 7; ++n) {
                 out[(G_D1 + n) * (int64_t)np + e] = 0.5 * m.gdet * m.d1[n];
