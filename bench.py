@@ -136,7 +136,13 @@ def main():
     stream = torch.cuda.Stream()
     ctx = grmhd.Context(cfg, P, stream=stream)
     print(f"[bench] {args.workload}: {zones} zones, warmup {args.warmup}", file=sys.stderr, flush=True)
-    ctx.steps(args.warmup)
+    # the launch-shape autotuner runs inside the warm-up (5 candidate shapes x 2 ordinary steps)
+    tuned = None
+    warm = args.warmup
+    if warm >= 10:
+        tuned = ctx.autotune(2)
+        warm -= 10
+    ctx.steps(warm)
     torch.cuda.synchronize()
     ctx.kernel_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -185,6 +191,7 @@ def main():
                    "cfl": cfg.cfl, "riemann": "llf"},
         "roofline": roofline,
         "kernels": kernels,
+        "autotune": [ln for ln in (tuned or "").splitlines() if ln.startswith("chosen")],
         "sim_time": t,
         "unfixed_cells": nfail,
     }

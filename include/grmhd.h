@@ -131,6 +131,12 @@ int grmhd_debug_fluxes(grmhd_ctx* ctx, int32_t d, double* F, double* cmax);
 int grmhd_kernel_timing(grmhd_ctx* ctx, int32_t on);
 int grmhd_kernel_times(grmhd_ctx* ctx, double* avg_ms, int64_t* launches, int32_t n);
 
+/* Autotuner: runs `steps_per_candidate` ordinary RK2 steps (CFL dt, counted in the run's time)
+ * under each candidate launch shape -- threads per workgroup 64/128/256 and the block-to-XCD
+ * order -- and keeps, per stage-kernel kind (ghosts, X1/X2/X3 fluxes, update), the fastest.
+ * Results do not depend on the shape.  `report` (may be NULL) receives a text summary. */
+int grmhd_autotune(grmhd_ctx* ctx, int32_t steps_per_candidate, char* report, int32_t report_len);
+
 void grmhd_destroy(grmhd_ctx* ctx);
 
 /* Text of the last error of the calling thread ("" if none). */
@@ -155,6 +161,9 @@ int grmhd_batch_admit(grmhd_batch* b, const grmhd_grid* grid, const grmhd_params
 
 /* Advance every unfinished job by up to `steps` RK2 steps (CFL dt per job); enqueue only. */
 int grmhd_batch_advance(grmhd_batch* b, int32_t steps);
+
+/* Autotuner of the ensemble's launch shapes (see grmhd_autotune); the steps count for the jobs. */
+int grmhd_batch_autotune(grmhd_batch* b, int32_t steps_per_candidate, char* report, int32_t report_len);
 
 /* Waits for the enqueued work, then lists up to `cap` finished jobs not yet reported. */
 int grmhd_batch_poll(grmhd_batch* b, int64_t* done_ids, int32_t cap, int32_t* n_done);

@@ -36,8 +36,16 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(GRMHD_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int BS = 256;
 enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_UPD, NK };
+
+// Launch shape of one stage-kernel kind: threads per workgroup and block order (bit 0 set:
+// XCD-contiguous).  The autotuner picks one per kind.
+struct Shape {
+    int bs = 256;
+    int sched = 1;
+};
+const Shape kCandidates[] = {{256, 1}, {128, 1}, {64, 1}, {256, 0}, {128, 0}};
+constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 // kernel kinds reported by grmhd_kernel_times
 enum { TK_BOUND = 0, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_DT, TK_UPDATE, TK_FIXUP, TK_SLOW, NTK };
 
@@ -282,6 +290,7 @@ struct Engine {
     std::vector<int> ev_kind;
     double t_ms[NTK] = {0};
     long long t_n[NTK] = {0};
+    Shape shape[NK];
 
     ~Engine() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -336,7 +345,7 @@ struct Engine {
             for (int r = 0; r < n; ++r) {
                 boff[kind * (cap + 1) + r] = acc;
                 const int64_t ne = elems(runs[r]->h, kind);
-                acc += (int)((ne + BS - 1) / BS);
+                acc += (int)((ne + shape[kind].bs - 1) / shape[kind].bs);
             }
             boff[kind * (cap + 1) + n] = acc;
             nblk[kind] = acc;
@@ -380,12 +389,14 @@ struct Engine {
         for (int stage = 1; stage <= 2; ++stage) {
             const int which = stage - 1;
             mark(TK_BOUND);
-            launch_bound(d_runs, boff(KB_BOUND), n, nblk[KB_BOUND], which, st);
+            launch_bound(d_runs, boff(KB_BOUND), n, nblk[KB_BOUND], which, shape[KB_BOUND].bs,
+                         shape[KB_BOUND].sched, st);
             mark(TK_BOUND);
             for (int d = 1; d <= 3; ++d) {
                 if (nblk[kf[d]] <= 0) continue;
                 mark(TK_FLUX1 + d - 1);
-                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, 0, st);
+                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, 0, shape[kf[d]].bs,
+                            shape[kf[d]].sched, st);
                 mark(TK_FLUX1 + d - 1);
             }
             if (stage == 1) {
@@ -394,7 +405,7 @@ struct Engine {
                 mark(TK_DT);
             }
             mark(TK_UPDATE);
-            launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, st);
+            launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, shape[KB_UPD].bs, shape[KB_UPD].sched, st);
             mark(TK_UPDATE);
             mark(TK_SLOW);
             launch_update_slow(d_runs, n, stage, st);
@@ -404,6 +415,51 @@ struct Engine {
             mark(TK_FIXUP);
         }
         HIPCHK(hipGetLastError());
+        return GRMHD_OK;
+    }
+    // Online autotuning: every candidate shape runs `reps` ordinary steps with per-kernel events;
+    // each kernel kind then keeps the shape with the smallest average duration.  A cell's
+    // arithmetic does not depend on the launch shape, so these are regular steps of the runs.
+    int autotune(int reps, std::string* report) {
+        if (runs.empty() || reps <= 0) return GRMHD_OK;
+        const int tk_of[NK] = {TK_BOUND, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_UPDATE};
+        double best_ms[NK];
+        int best[NK];
+        for (int k = 0; k < NK; ++k) { best_ms[k] = 1e300; best[k] = 0; }
+        const bool was_timing = timing;
+        char line[256];
+        for (int c = 0; c < kNumCandidates; ++c) {
+            for (int k = 0; k < NK; ++k) shape[k] = kCandidates[c];
+            dirty = true;
+            int rc = harvest();
+            if (rc) return rc;
+            for (int k = 0; k < NTK; ++k) { t_ms[k] = 0.0; t_n[k] = 0; }
+            timing = true;
+            rc = steps(reps);
+            if (rc == GRMHD_OK) rc = harvest();
+            timing = was_timing;
+            if (rc) return rc;
+            for (int k = 0; k < NK; ++k) {
+                const int tk = tk_of[k];
+                if (!t_n[tk]) continue;
+                const double ms = t_ms[tk] / (double)t_n[tk];
+                if (report) {
+                    snprintf(line, sizeof(line), "kind %d bs %d sched %d: %.4f ms\n", k, kCandidates[c].bs,
+                             kCandidates[c].sched, ms);
+                    *report += line;
+                }
+                if (ms < best_ms[k]) { best_ms[k] = ms; best[k] = c; }
+            }
+        }
+        for (int k = 0; k < NK; ++k) shape[k] = kCandidates[best[k]];
+        for (int k = 0; k < NTK; ++k) { t_ms[k] = 0.0; t_n[k] = 0; }
+        dirty = true;
+        if (report) {
+            for (int k = 0; k < NK; ++k) {
+                snprintf(line, sizeof(line), "chosen kind %d: bs %d sched %d\n", k, shape[k].bs, shape[k].sched);
+                *report += line;
+            }
+        }
         return GRMHD_OK;
     }
     int steps(int nsteps) {
@@ -691,8 +747,8 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     hipStream_t st = E.st;
     const int kind = d == 1 ? KB_F1 : (d == 2 ? KB_F2 : KB_F3);
     HIPCHK(hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st));
-    launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, st);
-    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, st);
+    launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, E.shape[KB_BOUND].bs, E.shape[KB_BOUND].sched, st);
+    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, E.shape[kind].bs, E.shape[kind].sched, st);
     const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
     double* dF = nullptr;
     HIPCHK(hipMalloc(&dF, n * 8));
@@ -707,6 +763,24 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     if (e != hipSuccess) return fail(GRMHD_EDEVICE, "debug_fluxes: %s", hipGetErrorString(e));
     if (cmax) std::memcpy(cmax, &bits[d - 1], sizeof(double));
     return GRMHD_OK;
+}
+
+static int copy_report(const std::string& r, char* out, int32_t len) {
+    if (out && len > 0) {
+        const size_t n = std::min((size_t)(len - 1), r.size());
+        std::memcpy(out, r.data(), n);
+        out[n] = '\0';
+    }
+    return GRMHD_OK;
+}
+
+int grmhd_autotune(grmhd_ctx* c, int32_t steps_per_candidate, char* report, int32_t report_len) {
+    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
+    if (steps_per_candidate < 1) return fail(GRMHD_EINVAL, "steps_per_candidate < 1");
+    std::string r;
+    int rc = c->eng.autotune(steps_per_candidate, &r);
+    if (rc) return rc;
+    return copy_report(r, report, report_len);
 }
 
 int grmhd_kernel_timing(grmhd_ctx* c, int32_t on) {
@@ -790,6 +864,15 @@ int grmhd_batch_advance(grmhd_batch* b, int32_t steps) {
     if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
     if (steps < 0) return fail(GRMHD_EINVAL, "steps < 0");
     return b->eng.steps(steps);
+}
+
+int grmhd_batch_autotune(grmhd_batch* b, int32_t steps_per_candidate, char* report, int32_t report_len) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    if (steps_per_candidate < 1) return fail(GRMHD_EINVAL, "steps_per_candidate < 1");
+    std::string r;
+    int rc = b->eng.autotune(steps_per_candidate, &r);
+    if (rc) return rc;
+    return copy_report(r, report, report_len);
 }
 
 int grmhd_batch_poll(grmhd_batch* b, int64_t* done_ids, int32_t cap, int32_t* n_done) {

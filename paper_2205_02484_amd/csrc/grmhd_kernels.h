@@ -14,12 +14,15 @@ struct GeoArgs {
 };
 
 void launch_geometry(const GeoArgs& A, hipStream_t st);
-void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, hipStream_t st);
+// bs: threads per workgroup (64, 128 or 256); sched bit 0: XCD-contiguous block order
+void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int bs, int sched,
+                  hipStream_t st);
 // ent = 1 also computes and stores the entropy component (diagnostics); the stage chain uses 0
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, hipStream_t st);
+                 int ent, int bs, int sched, hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
-void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st);
+void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int bs, int sched,
+                   hipStream_t st);
 void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st);
 void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st);
 void launch_load(const RunDev& R, const double* in, int to_half, hipStream_t st);

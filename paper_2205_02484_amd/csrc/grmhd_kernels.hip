@@ -137,8 +137,9 @@ __global__ void k_geometry(GeoArgs A) {
 // Each ghost is computed directly from its interior source, so one launch covers corners too.
 // ------------------------------------------------------------------------------------------
 
-__global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns, int which) {
-    const int bl = xcd_block(blockIdx.x, gridDim.x);
+__global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns, int which,
+                        int sched) {
+    const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
@@ -296,8 +297,8 @@ __device__ __forceinline__ double entropy_flux(const RunDev& R, int i, int j, in
 
 template <int D, bool ENT>
 __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
-                                              int nruns, int which, int do_cfl) {
-    const int bl = xcd_block(blockIdx.x, gridDim.x);
+                                              int nruns, int which, int do_cfl, int sched) {
+    const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
@@ -322,9 +323,9 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
             j = (int)(t % nj) + j0;
             i = (int)(t / nj) + i0;
         }
-        if (ENT) cw = flux_face<D, false, true>(R, i, j, k, which, nullptr);
-        else if (R.geo_uniform) cw = flux_face<D, true, false>(R, i, j, k, which, nullptr);
-        else cw = flux_face<D, false, false>(R, i, j, k, which, nullptr);
+        // one code path per kernel: keeping the scalar-metric variant beside the per-lane one costs
+        // ~30 VGPRs (3 instead of 4 waves per SIMD), more than the scalar loads save
+        cw = flux_face<D, false, ENT>(R, i, j, k, which, nullptr);
     }
     if (!do_cfl) return;
     __shared__ double red[4];
@@ -635,8 +636,8 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int stage, int64_t 
 }
 
 __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
-                                                int nruns, int stage) {
-    const int bl = xcd_block(blockIdx.x, gridDim.x);
+                                                int nruns, int stage, int sched) {
+    const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
@@ -919,21 +920,22 @@ void launch_geometry(const GeoArgs& A, hipStream_t st) {
     k_geometry<<<(np + 127) / 128, 128, 0, st>>>(A);
 }
 
-void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, hipStream_t st) {
-    if (nblocks > 0) k_bound<<<nblocks, 256, 0, st>>>(runs, boff, nruns, which);
+void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int bs, int sched,
+                  hipStream_t st) {
+    if (nblocks > 0) k_bound<<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, sched);
 }
 
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, hipStream_t st) {
+                 int ent, int bs, int sched, hipStream_t st) {
     if (nblocks <= 0) return;
     if (ent) {
-        if (d == 1) k_flux<1, true><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
-        else if (d == 2) k_flux<2, true><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
-        else k_flux<3, true><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+        if (d == 1) k_flux<1, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else if (d == 2) k_flux<2, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else k_flux<3, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
     } else {
-        if (d == 1) k_flux<1, false><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
-        else if (d == 2) k_flux<2, false><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
-        else k_flux<3, false><<<nblocks, 256, 0, st>>>(runs, boff, nruns, which, do_cfl);
+        if (d == 1) k_flux<1, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else if (d == 2) k_flux<2, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else k_flux<3, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
     }
 }
 
@@ -941,8 +943,9 @@ void launch_dt(const RunDev* runs, int nruns, hipStream_t st) {
     k_dt<<<(nruns + 63) / 64, 64, 0, st>>>(runs, nruns);
 }
 
-void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, hipStream_t st) {
-    if (nblocks > 0) k_update<<<nblocks, 256, 0, st>>>(runs, boff, nruns, stage);
+void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int bs, int sched,
+                   hipStream_t st) {
+    if (nblocks > 0) k_update<<<nblocks, bs, 0, st>>>(runs, boff, nruns, stage, sched);
 }
 
 void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st) {

@@ -24,8 +24,8 @@ LLF, HLL = 0, 1
 SYMBOLS = [
     "grmhd_params_default", "grmhd_init", "grmhd_step", "grmhd_steps", "grmhd_cons2prim",
     "grmhd_prim2cons", "grmhd_diag", "grmhd_get_prims", "grmhd_get_time", "grmhd_get_codes",
-    "grmhd_debug_fluxes", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
-    "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_poll",
+    "grmhd_debug_fluxes", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
+    "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_autotune", "grmhd_batch_poll",
     "grmhd_batch_fetch", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
 ]
 
@@ -81,6 +81,8 @@ def load(path: str = LIB_PATH):
     L.grmhd_debug_fluxes.argtypes = [vp, i32, vp, dp]
     L.grmhd_kernel_timing.argtypes = [vp, i32]
     L.grmhd_kernel_times.argtypes = [vp, dp, ctypes.POINTER(i64), i32]
+    L.grmhd_autotune.argtypes = [vp, i32, ctypes.c_char_p, i32]
+    L.grmhd_batch_autotune.argtypes = [vp, i32, ctypes.c_char_p, i32]
     L.grmhd_destroy.argtypes = [vp]
     L.grmhd_destroy.restype = None
     L.grmhd_last_error.argtypes = []
@@ -240,6 +242,11 @@ class Context:
         _check(load().grmhd_diag(self._h, ctypes.byref(m), ctypes.byref(f)))
         return m.value, f.value
 
+    def autotune(self, steps_per_candidate: int = 2) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().grmhd_autotune(self._h, int(steps_per_candidate), buf, len(buf)))
+        return buf.value.decode()
+
     KERNELS = ("bound", "flux1", "flux2", "flux3", "dt", "update", "fixup", "update_slow")
 
     def kernel_timing(self, on: bool):
@@ -291,6 +298,11 @@ class Batch:
 
     def advance(self, steps: int):
         _check(load().grmhd_batch_advance(self._h, int(steps)))
+
+    def autotune(self, steps_per_candidate: int = 2) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _check(load().grmhd_batch_autotune(self._h, int(steps_per_candidate), buf, len(buf)))
+        return buf.value.decode()
 
     def poll(self, cap: int = 1024):
         ids = (ctypes.c_int64 * cap)()

@@ -128,3 +128,21 @@ def test_errors_are_reported_not_raised_in_c(G):
     assert ei.value.code == G.EINVAL
     with pytest.raises(G.GrmhdError):
         G.Context(c, make_torus(c), spin=1.5, r_in_grid=1.0)
+
+
+def test_autotuned_launch_shapes_give_identical_results(G):
+    c = _cfgs()[1]
+    P = make_torus(c)
+    plain = G.Context(c, P)
+    tuned = G.Context(c, P)
+    report = tuned.autotune(1)              # 5 candidate shapes x 1 step
+    assert "chosen kind 4" in report
+    plain.steps(5)
+    tuned.steps(5 - 5)                      # the tuning steps already advanced the run by 5
+    assert plain.get_time() == tuned.get_time()
+    assert np.array_equal(plain.get_prims(), tuned.get_prims())
+    plain.steps(3)
+    tuned.steps(3)
+    assert np.array_equal(plain.get_prims(), tuned.get_prims())
+    plain.close()
+    tuned.close()
