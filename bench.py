@@ -25,6 +25,30 @@ sys.path.insert(0, ROOT)
 #   bound  : per ghost cell, 8 primitives read and written
 ALG_BYTES = {"flux1": 128.0, "flux2": 128.0, "flux3": 128.0, "update": 385.0, "bound": 128.0}
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("grmhd_dev.h", "grmhd_c2p.h", "grmhd_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2205_02484_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_counters(workload):
+    """Per-launch HBM bytes and FP64 FLOP of the committed rocprofv3 passes, or None when the
+    kernels have changed since they were taken (source hash) or the workload differs."""
+    try:
+        with open(COUNTERS) as fh:
+            js = json.load(fh)
+    except OSError:
+        return None
+    if js.get("workload") != workload or js.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return js["per_launch"]
 
 
 def units_per_launch(kind, n1, n2, n3):
@@ -167,9 +191,21 @@ def main():
     avg_ms = kt[dom][0]
     units = units_per_launch(dom, n1, n2, n3)
     achieved = ALG_BYTES[dom] * units / (avg_ms * 1e-3) / 1e9
+    prof = profiled_counters(args.workload)
+    traffic = None
+    if prof and dom in prof:
+        traffic = prof[dom]["hbm_read_bytes"] + prof[dom]["hbm_write_bytes"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
-                "avg_ms": avg_ms, "alg_bytes_per_unit": ALG_BYTES[dom], "units_per_launch": units}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                "avg_ms": avg_ms, "alg_bytes_per_unit": ALG_BYTES[dom], "units_per_launch": units,
+                "alg_bytes_per_launch": ALG_BYTES[dom] * units}
+    if prof:
+        # measured HBM and FP64 rates of every stage kernel at the live durations (context)
+        roofline["per_kernel_measured"] = {
+            k: {"hbm_GBs": (v["hbm_read_bytes"] + v["hbm_write_bytes"]) / (kt[k][0] * 1e-3) / 1e9,
+                "fp64_TFLOPs": v["fp64_flop"] / (kt[k][0] * 1e-3) / 1e12,
+                "fp64_frac": v["fp64_flop"] / (kt[k][0] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+            for k, v in prof.items() if k in kt and kt[k][0] > 0}
     kernels = {k: {"avg_ms": v[0], "launches": v[1], "share": tot[k] / max(sum(tot.values()), 1e-30)}
                for k, v in kt.items()}
 
