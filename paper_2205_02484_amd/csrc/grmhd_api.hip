@@ -36,7 +36,9 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(GRMHD_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_UPD, NK };
+// block tables: ghosts, fluxes per direction, update over runs with n3 % 64 == 0 (scalar metric)
+// and over the other runs
+enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_UPD, KB_UPDN, NK };
 
 // Launch shape of one stage-kernel kind: threads per workgroup and block order (bit 0 set:
 // XCD-contiguous).  The autotuner picks one per kind.
@@ -323,7 +325,8 @@ struct Engine {
             case KB_F1: return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
             case KB_F2: return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
             case KB_F3: return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3 : 0;
-            default: return n1 * n2 * n3;
+            case KB_UPD: return R.geo_uniform ? n1 * n2 * n3 : 0;
+            default: return R.geo_uniform ? 0 : n1 * n2 * n3;
         }
     }
     int rebuild() {
@@ -405,7 +408,9 @@ struct Engine {
                 mark(TK_DT);
             }
             mark(TK_UPDATE);
-            launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, shape[KB_UPD].bs, shape[KB_UPD].sched, st);
+            launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, 1, shape[KB_UPD].bs, shape[KB_UPD].sched, st);
+            launch_update(d_runs, boff(KB_UPDN), n, nblk[KB_UPDN], stage, 0, shape[KB_UPDN].bs, shape[KB_UPDN].sched,
+                          st);
             mark(TK_UPDATE);
             mark(TK_SLOW);
             launch_update_slow(d_runs, n, stage, st);
@@ -422,7 +427,7 @@ struct Engine {
     // arithmetic does not depend on the launch shape, so these are regular steps of the runs.
     int autotune(int reps, std::string* report) {
         if (runs.empty() || reps <= 0) return GRMHD_OK;
-        const int tk_of[NK] = {TK_BOUND, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_UPDATE};
+        const int tk_of[NK] = {TK_BOUND, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_UPDATE, TK_UPDATE};
         double best_ms[NK];
         int best[NK];
         for (int k = 0; k < NK; ++k) { best_ms[k] = 1e300; best[k] = 0; }

@@ -168,9 +168,8 @@ __device__ __forceinline__ void flux_of(const double* P, const St& s, const Geo&
 // k_mu = (-omega, k_D), as c1 >= c2 in omega/k_D.
 template <int D>
 __device__ __forceinline__ void wave_speeds(const St& s, const Geo& G, double gam, double& c1, double& c2) {
-    const double cs2 = gam * s.p / s.w;
-    const double va2 = s.bsq / (s.bsq + s.w);
-    const double cms2 = va2 + cs2 * (1.0 - va2);
+    // v_a^2 + c_s^2 (1 - v_a^2) with v_a^2 = b^2/(b^2 + w), c_s^2 = gam p / w, in one division
+    const double cms2 = (s.bsq + gam * s.p) / (s.bsq + s.w);
     const double ud = D == 1 ? s.u1 : (D == 2 ? s.u2 : s.u3);
     const double gtd = D == 1 ? G.Gt1 : 0.0;
     const double gdd = D == 1 ? G.G11 : (D == 2 ? G.G22 : G.G33);

@@ -21,8 +21,9 @@ void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, i
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
                  int ent, int bs, int sched, hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
-void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int bs, int sched,
-                   hipStream_t st);
+// uni = 1: the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
+void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int uni, int bs,
+                   int sched, hipStream_t st);
 void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st);
 void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st);
 void launch_load(const RunDev& R, const double* in, int to_half, hipStream_t st);

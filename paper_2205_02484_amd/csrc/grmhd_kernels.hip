@@ -405,9 +405,10 @@ __device__ __forceinline__ void source_terms(const St& s, const double* __restri
 // Conserved state after the stage update of interior cell (i,j,k): flux-CT, the flux divergence,
 // the centred source from the stage-input primitives Pg, U = U(P^n) + c dt L.  With ENT = false
 // the entropy component (used only by the entropy inversion) is skipped.
-template <bool ENT, bool UNI>
-__device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k, int stage, double* U, double* Pg,
+template <bool ENT, bool UNI, int STAGE>
+__device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k, double* U, double* Pg,
                                             Geo& G, St& sg, int64_t& gi_out) {
+    constexpr int stage = STAGE;
     const int n2 = R.n2, n3 = R.n3;
     const int64_t ci = cell_index(R, i, j, k);
     const int64_t vs = R.vs, s1 = R.s1, s2 = R.s2;
@@ -551,7 +552,13 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const double gam = R.gam;
     const double* __restrict__ Pn = R.P;
     const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
-    {
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) Pg[q] = Pin[q * vs + ci];
+    prim_state(Pg, G, gam, sg);
+    if (stage == 1) {
+        // the stage input is P^n itself: U(P^n) comes from the same state
+        flux_of<0>(Pg, sg, G, ENT ? sg.p * pow(Pg[0], 1.0 - gam) : 0.0, U);
+    } else {
         double P0[NPR];
 #pragma unroll
         for (int q = 0; q < NPR; ++q) P0[q] = Pn[q * vs + ci];
@@ -559,9 +566,6 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
         prim_state(P0, G, gam, s0);
         flux_of<0>(P0, s0, G, ENT ? s0.p * pow(P0[0], 1.0 - gam) : 0.0, U);
     }
-#pragma unroll
-    for (int q = 0; q < NPR; ++q) Pg[q] = Pin[q * vs + ci];
-    prim_state(Pg, G, gam, sg);
     double S[4];
     source_terms(sg, R.gc, R.gpts, gi, G, S);
     L[1] += S[0];
@@ -576,8 +580,9 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
 // Fast path of the inversion: Newton-Raphson accepted when converged and physical, floors, and
 // the Lorentz cap.  Cells that need the entropy method (beta switch), Brent, or a magnetisation
 // ceiling go to the run's slow list and are finished by k_update_slow with the full procedure.
-template <bool UNI>
-__device__ __forceinline__ void update_fast(const RunDev& R, int stage, int64_t e) {
+template <bool UNI, int STAGE>
+__device__ __forceinline__ void update_fast(const RunDev& R, int64_t e) {
+    constexpr int stage = STAGE;
     const int n2 = R.n2, n3 = R.n3;
     const int k = (int)(e % n3);
     const int64_t t = e / n3;
@@ -587,7 +592,7 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int stage, int64_t 
     Geo G;
     St sg;
     int64_t gi;
-    stage_state<false, UNI>(R, i, j, k, stage, U, Pg, G, sg, gi);
+    stage_state<false, UNI, STAGE>(R, i, j, k, U, Pg, G, sg, gi);
     bool slow = sg.p < R.beta_ent * 0.5 * sg.bsq;
     double P[NPR];
     if (!slow) {
@@ -635,16 +640,19 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int stage, int64_t 
     for (int q = 0; q < NPR; ++q) Pout[q * R.vs + ci] = P[q];
 }
 
+// UNI: the launch covers only runs whose n3 is a multiple of 64 (a wave's cells share (r, theta),
+// metric by scalar loads); the engine keeps a separate block table for the other runs.  One code
+// path per instantiation keeps the register count at 4 waves per SIMD.
+template <int STAGE, bool UNI>
 __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
-                                                int nruns, int stage, int sched) {
+                                                int nruns, int sched) {
     const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
     const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
     if (e >= (int64_t)R.n1 * R.n2 * R.n3) return;
-    if (R.geo_uniform) update_fast<true>(R, stage, e);
-    else update_fast<false>(R, stage, e);
+    update_fast<UNI, STAGE>(R, e);
 }
 
 // Slow path: the full inversion (beta switch, NR, Brent on W, entropy) and the full floors with
@@ -664,7 +672,8 @@ __global__ __launch_bounds__(256) void k_update_slow(const RunDev* __restrict__ 
         Geo G;
         St sg;
         int64_t gi;
-        stage_state<true, false>(R, i, j, k, stage, U, Pg, G, sg, gi);
+        if (stage == 1) stage_state<true, false, 1>(R, i, j, k, U, Pg, G, sg, gi);
+        else stage_state<true, false, 2>(R, i, j, k, U, Pg, G, sg, gi);
         double P[NPR];
 #pragma unroll
         for (int q = 0; q < NPR; ++q) P[q] = Pg[q];
@@ -943,9 +952,16 @@ void launch_dt(const RunDev* runs, int nruns, hipStream_t st) {
     k_dt<<<(nruns + 63) / 64, 64, 0, st>>>(runs, nruns);
 }
 
-void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int bs, int sched,
-                   hipStream_t st) {
-    if (nblocks > 0) k_update<<<nblocks, bs, 0, st>>>(runs, boff, nruns, stage, sched);
+void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int uni, int bs,
+                   int sched, hipStream_t st) {
+    if (nblocks <= 0) return;
+    if (uni) {
+        if (stage == 1) k_update<1, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, sched);
+        else k_update<2, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, sched);
+    } else {
+        if (stage == 1) k_update<1, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, sched);
+        else k_update<2, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, sched);
+    }
 }
 
 void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st) {
