@@ -89,6 +89,9 @@ int validate(const grmhd_grid* g, const grmhd_params* p) {
     if (!g || !p) return fail(GRMHD_EINVAL, "grid and params are required");
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) return fail(GRMHD_EINVAL, "grid sizes must be >= 1");
     if ((int64_t)g->n1 * g->n2 * g->n3 >= (1ll << 31)) return fail(GRMHD_EINVAL, "grid too large (>= 2^31 cells)");
+    // every per-variable array is addressed with 32-bit byte offsets: (n1+4)(n2+4) n3 cells < 2^29
+    if ((int64_t)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * g->n3 >= (1ll << 29))
+        return fail(GRMHD_EINVAL, "grid too large for one run (more than 2^29 cells with ghosts)");
     if (g->coords != GRMHD_MKS && g->coords != GRMHD_MINKOWSKI_CART) return fail(GRMHD_EINVAL, "unknown coords");
     if (g->coords == GRMHD_MKS) {
         if (g->n1 < 2 || g->n2 < 2) return fail(GRMHD_EINVAL, "MKS grids need n1, n2 >= 2");

@@ -65,6 +65,19 @@ struct RunVar {
     int32_t fail_count, active, nfail_last, slow_count;
 };
 
+// Global-memory access through a wave-uniform base pointer and a 32-bit element index: the
+// compiler then issues global_load/store with an SGPR base and a VGPR byte offset, with no 64-bit
+// address arithmetic per access.  Every array is < 4 GiB (checked when a run is created).
+typedef __attribute__((address_space(1))) char g_char;
+typedef __attribute__((address_space(1))) double g_double;
+
+__device__ __forceinline__ double gld(const double* base, uint32_t e) {
+    return *(const g_double*)((const g_char*)base + e * 8u);
+}
+__device__ __forceinline__ void gst(double* base, uint32_t e, double v) {
+    *(g_double*)((g_char*)base + e * 8u) = v;
+}
+
 __device__ __forceinline__ int64_t cell_index(const RunDev& R, int i, int j, int k) {
     return (int64_t)(i + NG) * R.s1 + (int64_t)(j + NG) * R.s2 + k;
 }
@@ -78,23 +91,24 @@ struct Geo {
     double gdet, alpha, ialpha;
 };
 
-__device__ __forceinline__ void load_geo(const double* __restrict__ g, int64_t np, int64_t gi, Geo& G) {
-    G.gtt = g[G_TT * np + gi];
-    G.gt1 = g[G_T1 * np + gi];
-    G.gt3 = g[G_T3 * np + gi];
-    G.g11 = g[G_11 * np + gi];
-    G.g13 = g[G_13 * np + gi];
-    G.g22 = g[G_22 * np + gi];
-    G.g33 = g[G_33 * np + gi];
-    G.Gtt = g[GI_TT * np + gi];
-    G.Gt1 = g[GI_T1 * np + gi];
-    G.G11 = g[GI_11 * np + gi];
-    G.G13 = g[GI_13 * np + gi];
-    G.G22 = g[GI_22 * np + gi];
-    G.G33 = g[GI_33 * np + gi];
-    G.gdet = g[G_DET * np + gi];
-    G.alpha = g[G_ALPHA * np + gi];
-    G.ialpha = g[G_IALPHA * np + gi];
+__device__ __forceinline__ void load_geo(const double* __restrict__ g, int64_t np, int64_t gi64, Geo& G) {
+    const uint32_t gi = (uint32_t)gi64;
+    G.gtt = gld(g + G_TT * np, gi);
+    G.gt1 = gld(g + G_T1 * np, gi);
+    G.gt3 = gld(g + G_T3 * np, gi);
+    G.g11 = gld(g + G_11 * np, gi);
+    G.g13 = gld(g + G_13 * np, gi);
+    G.g22 = gld(g + G_22 * np, gi);
+    G.g33 = gld(g + G_33 * np, gi);
+    G.Gtt = gld(g + GI_TT * np, gi);
+    G.Gt1 = gld(g + GI_T1 * np, gi);
+    G.G11 = gld(g + GI_11 * np, gi);
+    G.G13 = gld(g + GI_13 * np, gi);
+    G.G22 = gld(g + GI_22 * np, gi);
+    G.G33 = gld(g + GI_33 * np, gi);
+    G.gdet = gld(g + G_DET * np, gi);
+    G.alpha = gld(g + G_ALPHA * np, gi);
+    G.ialpha = gld(g + G_IALPHA * np, gi);
 }
 
 // 4-velocity, field 4-vector and thermodynamics of one primitive state.

@@ -173,7 +173,7 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
     const int64_t src = cell_index(R, is, js, k), dst = cell_index(R, i, j, k);
     double v[NPR];
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) v[q] = P[q * R.vs + src];
+    for (int q = 0; q < NPR; ++q) v[q] = gld(P + q * R.vs, (uint32_t)src);
     if (R.mks) {
         if (i != is) {
             const int64_t np = R.gpts;
@@ -186,7 +186,7 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
         }
     }
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) P[q * R.vs + dst] = v[q];
+    for (int q = 0; q < NPR; ++q) gst(P + q * R.vs, (uint32_t)dst, v[q]);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -217,7 +217,7 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
             return 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) F[q * R.vs + ci] = 0.0;
+        for (int q = 0; q < NQ; ++q) gst(F + q * R.vs, (uint32_t)ci, 0.0);
         return 0.0;
     }
     const double* __restrict__ P = which ? R.Ph : R.P;
@@ -234,7 +234,8 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
 #pragma unroll
     for (int q = 0; q < NPR; ++q) {
         const double* Pq = P + q * R.vs;
-        const double a = Pq[cm2], b = Pq[cm1], c = Pq[ci], d = Pq[cp1];
+        const double a = gld(Pq, (uint32_t)cm2), b = gld(Pq, (uint32_t)cm1), c = gld(Pq, (uint32_t)ci),
+                     d = gld(Pq, (uint32_t)cp1);
         Pl[q] = b + 0.5 * mc_slope(a, b, c);
         Pr[q] = c - 0.5 * mc_slope(b, c, d);
     }
@@ -281,7 +282,7 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         return 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) F[q * R.vs + ci] = out[q];
+    for (int q = 0; q < NQ; ++q) gst(F + q * R.vs, (uint32_t)ci, out[q]);
     if (D != 1 && (i < 0 || i >= n1)) return 0.0;
     if (D != 2 && (j < 0 || j >= n2)) return 0.0;
     return cwf;
@@ -393,8 +394,8 @@ __device__ __forceinline__ void source_terms(const St& s, const double* __restri
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int n = 0; n < 7; ++n) {
-        s1 += mult[n] * T[n] * gc[(G_D1 + n) * np + gi];
-        s2 += mult[n] * T[n] * gc[(G_D2 + n) * np + gi];
+        s1 += mult[n] * T[n] * gld(gc + (G_D1 + n) * np, (uint32_t)gi);
+        s2 += mult[n] * T[n] * gld(gc + (G_D2 + n) * np, (uint32_t)gi);
     }
     S[0] = 0.0;
     S[1] = s1;
@@ -440,7 +441,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 if (q >= 5 && q <= 7) continue;
-                L[q] -= (F1[q * vs + cp] - F1[q * vs + ci]) * R.idx[1];
+                L[q] -= (gld(F1 + q * vs, (uint32_t)cp) - gld(F1 + q * vs, (uint32_t)ci)) * R.idx[1];
             }
         }
         if (R.act2) {
@@ -448,31 +449,31 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 if (q >= 5 && q <= 7) continue;
-                L[q] -= (F2[q * vs + cq] - F2[q * vs + ci]) * R.idx[2];
+                L[q] -= (gld(F2 + q * vs, (uint32_t)cq) - gld(F2 + q * vs, (uint32_t)ci)) * R.idx[2];
             }
         }
         if (R.act3) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 if (q >= 5 && q <= 7) continue;
-                L[q] -= (F3[q * vs + ckp] - F3[q * vs + ci]) * R.idx[3];
+                L[q] -= (gld(F3 + q * vs, (uint32_t)ckp) - gld(F3 + q * vs, (uint32_t)ci)) * R.idx[3];
             }
         }
         // field components: F^d(B^d) = 0; transverse ones from edge EMFs where they exist
         double f1b2m = 0.0, f1b2p = 0.0, f1b3m = 0.0, f1b3p = 0.0;
         if (R.act1) {
-            f1b2m = F1[6 * vs + ci]; f1b2p = F1[6 * vs + cp];
-            f1b3m = F1[7 * vs + ci]; f1b3p = F1[7 * vs + cp];
+            f1b2m = gld(F1 + 6 * vs, (uint32_t)ci); f1b2p = gld(F1 + 6 * vs, (uint32_t)cp);
+            f1b3m = gld(F1 + 7 * vs, (uint32_t)ci); f1b3p = gld(F1 + 7 * vs, (uint32_t)cp);
         }
         double f2b1m = 0.0, f2b1p = 0.0, f2b3m = 0.0, f2b3p = 0.0;
         double f3b1m = 0.0, f3b1p = 0.0, f3b2m = 0.0, f3b2p = 0.0;
         if (R.act2) {
-            f2b1m = F2[5 * vs + ci]; f2b1p = F2[5 * vs + ci + s2];
-            f2b3m = F2[7 * vs + ci]; f2b3p = F2[7 * vs + ci + s2];
+            f2b1m = gld(F2 + 5 * vs, (uint32_t)ci); f2b1p = gld(F2 + 5 * vs, (uint32_t)(ci + s2));
+            f2b3m = gld(F2 + 7 * vs, (uint32_t)ci); f2b3p = gld(F2 + 7 * vs, (uint32_t)(ci + s2));
         }
         if (R.act3) {
-            f3b1m = F3[5 * vs + ci]; f3b1p = F3[5 * vs + ckp];
-            f3b2m = F3[6 * vs + ci]; f3b2p = F3[6 * vs + ckp];
+            f3b1m = gld(F3 + 5 * vs, (uint32_t)ci); f3b1p = gld(F3 + 5 * vs, (uint32_t)ckp);
+            f3b2m = gld(F3 + 6 * vs, (uint32_t)ci); f3b2p = gld(F3 + 6 * vs, (uint32_t)ckp);
         }
         if (has3) {
             // E3 at the four edges (i'-1/2, j'-1/2), i' in {i,i+1}, j' in {j,j+1}
@@ -486,7 +487,8 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
                     const int jj = j + b;
                     if (R.mks && (jj == 0 || jj == n2)) { E[a][b] = 0.0; continue; }
                     const int64_t c = ci + a * s1 + b * s2;
-                    E[a][b] = 0.25 * (F1b2[c - s2] + F1b2[c] - F2b1[c - s1] - F2b1[c]);
+                    E[a][b] = 0.25 * (gld(F1b2, (uint32_t)(c - s2)) + gld(F1b2, (uint32_t)c) -
+                                      gld(F2b1, (uint32_t)(c - s1)) - gld(F2b1, (uint32_t)c));
                 }
             f1b2m = 0.5 * (E[0][0] + E[0][1]);
             f1b2p = 0.5 * (E[1][0] + E[1][1]);
@@ -506,7 +508,8 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
                     if (R.mks && (jj == 0 || jj == n2)) { E[b][c] = 0.0; continue; }
                     const int64_t kk = c == 0 ? ci : ckp;        // cell/face k' index
                     const int64_t kk1 = c == 0 ? ckm : ci;       // k'-1
-                    E[b][c] = 0.25 * (F2b3[kk1 + b * s2] + F2b3[kk + b * s2] - F3b2[kk + (b - 1) * s2] - F3b2[kk + b * s2]);
+                    E[b][c] = 0.25 * (gld(F2b3, (uint32_t)(kk1 + b * s2)) + gld(F2b3, (uint32_t)(kk + b * s2)) -
+                                      gld(F3b2, (uint32_t)(kk + (b - 1) * s2)) - gld(F3b2, (uint32_t)(kk + b * s2)));
                 }
             f2b3m = 0.5 * (E[0][0] + E[0][1]);
             f2b3p = 0.5 * (E[1][0] + E[1][1]);
@@ -524,7 +527,8 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
                 for (int c = 0; c < 2; ++c) {
                     const int64_t kk = c == 0 ? ci : ckp;
                     const int64_t kk1 = c == 0 ? ckm : ci;
-                    E[a][c] = 0.25 * (F3b1[kk + (a - 1) * s1] + F3b1[kk + a * s1] - F1b3[kk1 + a * s1] - F1b3[kk + a * s1]);
+                    E[a][c] = 0.25 * (gld(F3b1, (uint32_t)(kk + (a - 1) * s1)) + gld(F3b1, (uint32_t)(kk + a * s1)) -
+                                      gld(F1b3, (uint32_t)(kk1 + a * s1)) - gld(F1b3, (uint32_t)(kk + a * s1)));
                 }
             f1b3m = -0.5 * (E[0][0] + E[0][1]);
             f1b3p = -0.5 * (E[1][0] + E[1][1]);
@@ -553,7 +557,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const double* __restrict__ Pn = R.P;
     const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) Pg[q] = Pin[q * vs + ci];
+    for (int q = 0; q < NPR; ++q) Pg[q] = gld(Pin + q * vs, (uint32_t)ci);
     prim_state(Pg, G, gam, sg);
     if (stage == 1) {
         // the stage input is P^n itself: U(P^n) comes from the same state
@@ -561,7 +565,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     } else {
         double P0[NPR];
 #pragma unroll
-        for (int q = 0; q < NPR; ++q) P0[q] = Pn[q * vs + ci];
+        for (int q = 0; q < NPR; ++q) P0[q] = gld(Pn + q * vs, (uint32_t)ci);
         St s0;
         prim_state(P0, G, gam, s0);
         flux_of<0>(P0, s0, G, ENT ? s0.p * pow(P0[0], 1.0 - gam) : 0.0, U);
@@ -614,8 +618,8 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int64_t e) {
                 P[5] = U[5] * ig;
                 P[6] = U[6] * ig;
                 P[7] = U[7] * ig;
-                P[0] = fmax(P[0], R.gc[G_RHOFL * R.gpts + gi]);
-                P[1] = fmax(P[1], R.gc[G_UFL * R.gpts + gi]);
+                P[0] = fmax(P[0], gld(R.gc + G_RHOFL * R.gpts, (uint32_t)gi));
+                P[1] = fmax(P[1], gld(R.gc + G_UFL * R.gpts, (uint32_t)gi));
                 St s;
                 prim_state(P, G, R.gam, s);
                 slow = (s.bsq / R.bsq_rho_max - P[0] > 0.0) || (s.bsq / R.bsq_u_max - P[1] > 0.0);
@@ -637,7 +641,7 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int64_t e) {
     double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
     R.code[ci] = 0;
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) Pout[q * R.vs + ci] = P[q];
+    for (int q = 0; q < NPR; ++q) gst(Pout + q * R.vs, (uint32_t)ci, P[q]);
 }
 
 // UNI: the launch covers only runs whose n3 is a multiple of 64 (a wave's cells share (r, theta),
