@@ -81,7 +81,9 @@ void grmhd_params_default(grmhd_params* p);
  * supplies a floored state) and builds the metric, inverse-metric and source tables (Sec. 4.1
  * metric, Sec. 2.2 centred source) on the device.  `hip_stream` is a hipStream_t the context
  * launches on (NULL: the library creates a non-blocking stream of its own).  EINVAL on bad
- * sizes/NaN, ENOMEM when the device state does not fit. */
+ * sizes/NaN or when (n1+4)(n2+4)n3 >= 2^29 (each per-variable device array, ghosts included,
+ * must stay below 4 GiB: kernels address it with 32-bit byte offsets; about 800^3 cells per run),
+ * ENOMEM when the device state does not fit. */
 int grmhd_init(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_params* params,
                const double* prims, int32_t prims_on_device, void* hip_stream);
 

@@ -36,9 +36,9 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(GRMHD_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-// block tables: ghosts, fluxes per direction, update over runs with n3 % 64 == 0 (scalar metric)
-// and over the other runs
-enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_UPD, KB_UPDN, NK };
+// block tables: ghosts; fluxes per direction and update, each once over the runs with n3 % 64 == 0
+// (a wave's cells share (r, theta): scalar metric loads) and once over the other runs
+enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_F1N, KB_F2N, KB_F3N, KB_UPD, KB_UPDN, NK };
 
 // Launch shape of one stage-kernel kind: threads per workgroup and block order (bit 0 set:
 // XCD-contiguous).  The autotuner picks one per kind.
@@ -83,6 +83,16 @@ Layout make_layout(const grmhd_grid& g) {
     L.off_var = take(sizeof(RunVar));
     L.total = o;
     return L;
+}
+
+// Multiplier and shift of FastDiv for a divisor 1 <= d < 2^31 (see grmhd_dev.h).
+FastDiv make_fastdiv(int32_t d) {
+    uint32_t l = 0;
+    while ((1ull << l) < (uint64_t)d) ++l;
+    FastDiv f;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - (uint64_t)d)) / (uint64_t)d + 1);
+    f.l = l;
+    return f;
 }
 
 int validate(const grmhd_grid* g, const grmhd_params* p) {
@@ -208,6 +218,8 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     for (int d = 0; d < 4; ++d) R.idx[d] = d ? 1.0 / R.dx[d] : 0.0;
     R.gam = p->gam;
     R.cfl = p->cfl;
+    R.gg = (p->gam - 1.0) / p->gam;
+    R.igam1 = 1.0 / (p->gam - 1.0);
     R.bsq_rho_max = p->bsq_rho_max;
     R.bsq_u_max = p->bsq_u_max;
     R.gamma_max = p->gamma_max;
@@ -226,6 +238,13 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.slow_list = (int32_t*)(r->mem + L.off_slow);
     R.geo_uniform = (g->n3 % 64) == 0;
     R.var = (RunVar*)(r->mem + L.off_var);
+    R.fd_n2 = make_fastdiv(g->n2);
+    R.fd_n3 = make_fastdiv(g->n3);
+    R.fd_kc = make_fastdiv(R.geo_uniform ? g->n3 / 64 : 1);
+    R.fd_row[0] = make_fastdiv(1);
+    R.fd_row[1] = make_fastdiv(g->n1 + 1);
+    R.fd_row[2] = make_fastdiv(g->n2 + 1);
+    R.fd_row[3] = make_fastdiv(g->n2 + 2 * R.act2);
 
     auto bail = [&](int code) { free_run(r); return code; };
     if (hipMemsetAsync(r->mem, 0, L.total, st) != hipSuccess) return bail(fail(GRMHD_EDEVICE, "memset failed"));
@@ -321,14 +340,19 @@ struct Engine {
         use_graph = !(ng && ng[0] == '1');
         return GRMHD_OK;
     }
-    static int64_t elems(const RunDev& R, int kind) {
+    static int64_t elems(const RunDev& R, int kind, int bs) {
         const int64_t n1 = R.n1, n2 = R.n2, n3 = R.n3;
         switch (kind) {
             case KB_BOUND: return (4 * (n2 + 2 * NG) + 4 * n1) * n3;
-            case KB_F1: return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
-            case KB_F2: return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
-            case KB_F3: return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3 : 0;
-            case KB_UPD: return R.geo_uniform ? n1 * n2 * n3 : 0;
+            case KB_F1: case KB_F1N:
+                return R.act1 && (kind == KB_F1) == (bool)R.geo_uniform ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
+            case KB_F2: case KB_F2N:
+                return R.act2 && (kind == KB_F2) == (bool)R.geo_uniform ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
+            case KB_F3: case KB_F3N:
+                return R.act3 && (kind == KB_F3) == (bool)R.geo_uniform ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3
+                                                                         : 0;
+            // uniform-metric update: workgroups of bs/64 waves tile i, rows padded to that tile
+            case KB_UPD: return R.geo_uniform ? (n1 + bs / 64 - 1) / (bs / 64) * (bs / 64) * n2 * n3 : 0;
             default: return R.geo_uniform ? 0 : n1 * n2 * n3;
         }
     }
@@ -350,7 +374,7 @@ struct Engine {
             int acc = 0;
             for (int r = 0; r < n; ++r) {
                 boff[kind * (cap + 1) + r] = acc;
-                const int64_t ne = elems(runs[r]->h, kind);
+                const int64_t ne = elems(runs[r]->h, kind, shape[kind].bs);
                 acc += (int)((ne + shape[kind].bs - 1) / shape[kind].bs);
             }
             boff[kind * (cap + 1) + n] = acc;
@@ -392,6 +416,7 @@ struct Engine {
         const int n = (int)runs.size();
         if (!n) return GRMHD_OK;
         const int kf[4] = {0, KB_F1, KB_F2, KB_F3};
+        const int kfn[4] = {0, KB_F1N, KB_F2N, KB_F3N};
         for (int stage = 1; stage <= 2; ++stage) {
             const int which = stage - 1;
             mark(TK_BOUND);
@@ -399,10 +424,12 @@ struct Engine {
                          shape[KB_BOUND].sched, st);
             mark(TK_BOUND);
             for (int d = 1; d <= 3; ++d) {
-                if (nblk[kf[d]] <= 0) continue;
+                if (nblk[kf[d]] <= 0 && nblk[kfn[d]] <= 0) continue;
                 mark(TK_FLUX1 + d - 1);
-                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, 0, shape[kf[d]].bs,
+                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, 0, 1, shape[kf[d]].bs,
                             shape[kf[d]].sched, st);
+                launch_flux(d, d_runs, boff(kfn[d]), n, nblk[kfn[d]], which, stage == 1, 0, 0, shape[kfn[d]].bs,
+                            shape[kfn[d]].sched, st);
                 mark(TK_FLUX1 + d - 1);
             }
             if (stage == 1) {
@@ -430,7 +457,7 @@ struct Engine {
     // arithmetic does not depend on the launch shape, so these are regular steps of the runs.
     int autotune(int reps, std::string* report) {
         if (runs.empty() || reps <= 0) return GRMHD_OK;
-        const int tk_of[NK] = {TK_BOUND, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_UPDATE, TK_UPDATE};
+        const int tk_of[NK] = {TK_BOUND, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_UPDATE, TK_UPDATE};
         double best_ms[NK];
         int best[NK];
         for (int k = 0; k < NK; ++k) { best_ms[k] = 1e300; best[k] = 0; }
@@ -753,10 +780,13 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
         if (rc) return rc;
     }
     hipStream_t st = E.st;
-    const int kind = d == 1 ? KB_F1 : (d == 2 ? KB_F2 : KB_F3);
+    // the context's one run sits in the uniform-metric or the general table; the entropy-carrying
+    // flux kernel used here reads the metric per lane and serves either
+    const int kind = R.geo_uniform ? (d == 1 ? KB_F1 : (d == 2 ? KB_F2 : KB_F3))
+                                   : (d == 1 ? KB_F1N : (d == 2 ? KB_F2N : KB_F3N));
     HIPCHK(hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st));
     launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, E.shape[KB_BOUND].bs, E.shape[KB_BOUND].sched, st);
-    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, E.shape[kind].bs, E.shape[kind].sched, st);
+    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, 0, E.shape[kind].bs, E.shape[kind].sched, st);
     const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
     double* dF = nullptr;
     HIPCHK(hipMalloc(&dF, n * 8));

@@ -21,13 +21,17 @@ struct Inv {
     double Qdotn, Qtsq, QdB, Bsq;
     double Bc1, Bc2, Bc3;           // frak B^i = alpha B^i
     double ent;                     // alpha U_S / sqrt(-g)
-    double gam;
+    double gam, gg, igam1;          // gamma, (gamma-1)/gamma, 1/(gamma-1)
+    double ig;                      // 1/sqrt(-g)
     double n1;                      // n^1 = -alpha g^{t1}  (n^2 = n^3 = 0)
 };
 
-__device__ __forceinline__ void inv_setup(const double* U, const Geo& G, double gam, Inv& q) {
-    const double f = G.alpha / G.gdet;
-    q.gam = gam;
+__device__ __forceinline__ void inv_setup(const double* U, const Geo& G, const RunDev& R, Inv& q) {
+    q.ig = 1.0 / G.gdet;
+    const double f = G.alpha * q.ig;
+    q.gam = R.gam;
+    q.gg = R.gg;
+    q.igam1 = R.igam1;
     q.D = f * U[0];
     q.Qt = f * U[1];
     q.Q1 = f * U[2];
@@ -39,7 +43,7 @@ __device__ __forceinline__ void inv_setup(const double* U, const Geo& G, double 
     q.ent = f * U[8];
     q.n1 = -G.alpha * G.Gt1;
     // n^t = 1/alpha
-    q.Qdotn = q.Qt / G.alpha + q.Q1 * q.n1;
+    q.Qdotn = q.Qt * G.ialpha + q.Q1 * q.n1;
     const double Qut = G.Gtt * q.Qt + G.Gt1 * q.Q1;
     q.Qu1 = G.Gt1 * q.Qt + G.G11 * q.Q1 + G.G13 * q.Q3;
     const double Qu2 = G.G22 * q.Q2;
@@ -51,7 +55,11 @@ __device__ __forceinline__ void inv_setup(const double* U, const Geo& G, double 
 }
 
 __device__ __forceinline__ double p_of_w(const Inv& q, double W, double v2) {
-    return ((q.gam - 1.0) / q.gam) * (W * (1.0 - v2) - q.D * sqrt(1.0 - v2));
+    return q.gg * (W * (1.0 - v2) - q.D * sqrt(1.0 - v2));
+}
+// the same with sq = sqrt(1 - v^2) at hand
+__device__ __forceinline__ double p_of_w_sq(const Inv& q, double W, double v2, double sq) {
+    return q.gg * (W * (1.0 - v2) - q.D * sq);
 }
 __device__ __forceinline__ double inv1(const Inv& q, double W, double v2) {
     const double bw = q.Bsq + W;
@@ -125,11 +133,13 @@ __device__ __forceinline__ bool is_physical(double W, double v2, double rho, dou
            v2 < 1.0 && rho > 0.0 && p > 0.0;
 }
 
-// u~^i = Gamma/(W + B^2) (Q~^i + (Q.B) B^i / W), Q~^i = Q^i + n^i (Q.n)
-__device__ __forceinline__ void velocity_out(const Inv& q, const Geo& G, double W, double v2, double* P) {
-    const double lor = 1.0 / sqrt(1.0 - v2);
-    const double f = lor / (W + q.Bsq);
-    const double g = q.QdB / W;
+// u~^i = Gamma/(W + B^2) (Q~^i + (Q.B) B^i / W), Q~^i = Q^i + n^i (Q.n); lor = Gamma.  Both
+// quotients come from one reciprocal of W (W + B^2).
+__device__ __forceinline__ void velocity_out(const Inv& q, const Geo& G, double W, double lor, double* P) {
+    const double bw = W + q.Bsq;
+    const double iw = 1.0 / (W * bw);
+    const double f = lor * W * iw;
+    const double g = q.QdB * bw * iw;
     P[2] = f * (q.Qu1 + q.n1 * q.Qdotn + g * q.Bc1);
     P[3] = f * (G.G22 * q.Q2 + g * q.Bc2);
     P[4] = f * (q.Qu3 + g * q.Bc3);
@@ -137,20 +147,21 @@ __device__ __forceinline__ void velocity_out(const Inv& q, const Geo& G, double 
 
 // 2D Newton-Raphson on (W, v^2); true when |dW| < tol W.
 __device__ __forceinline__ bool newton2d(const Inv& q, double tol, int maxit, double& W, double& v2) {
-    const double gg = (q.gam - 1.0) / q.gam;
+    const double gg = q.gg;
     const double qb2 = q.QdB * q.QdB;
     for (int it = 0; it < maxit; ++it) {
         const double bw = q.Bsq + W;
         const double iW = 1.0 / W;
         const double iW2 = iW * iW;
-        const double sq = sqrt(1.0 - v2);
+        double sq, isq;
+        sqrt_rsqrt(1.0 - v2, sq, isq);  // v2 in [0, 1 - 1e-12]
         const double pg = gg * (W * (1.0 - v2) - q.D * sq);
         const double f1 = v2 * bw * bw - qb2 * (q.Bsq + 2.0 * W) * iW2 - q.Qtsq;
         const double f2 = -0.5 * q.Bsq * (1.0 + v2) + 0.5 * qb2 * iW2 - W + pg - q.Qdotn;
         const double j11 = 2.0 * v2 * bw + 2.0 * qb2 * bw * iW2 * iW;
         const double j12 = bw * bw;
         const double j21 = -qb2 * iW2 * iW - 1.0 + gg * (1.0 - v2);
-        const double j22 = -0.5 * q.Bsq + gg * (-W + q.D / (2.0 * sq));
+        const double j22 = -0.5 * q.Bsq + gg * (-W + 0.5 * q.D * isq);
         const double idet = 1.0 / (j11 * j22 - j12 * j21);
         const double dW = -(f1 * j22 - f2 * j12) * idet;
         const double dv = -(j11 * f2 - j21 * f1) * idet;
@@ -162,20 +173,26 @@ __device__ __forceinline__ bool newton2d(const Inv& q, double tol, int maxit, do
     return false;
 }
 
+// Primitives from a root (W, v^2) of the energy equations, v^2 in [0, 1 - 1e-12]; false when the
+// state is not physical (P untouched then).
+__device__ __forceinline__ bool finish_energy(const Inv& q, const Geo& G, double W, double v2, double* P) {
+    double sq, lor;
+    sqrt_rsqrt(1.0 - v2, sq, lor);
+    const double rho = q.D * sq;
+    const double p = p_of_w_sq(q, W, v2, sq);
+    if (!is_physical(W, v2, rho, p)) return false;
+    P[0] = rho;
+    P[1] = p * q.igam1;
+    velocity_out(q, G, W, lor, P);
+    return true;
+}
+
 // Energy-equation inversion: 0 (NR), 1 (Brent on W), -1 (NR converged to a non-physical
 // state), -2 (no solution).
 __device__ __forceinline__ int invert_energy(const Inv& q, const Geo& G, double W0, double v20, double tol,
                                              int maxit, double* P) {
     double W = W0, v2 = v20;
-    if (newton2d(q, tol, maxit, W, v2)) {
-        const double rho = q.D * sqrt(1.0 - v2);
-        const double p = p_of_w(q, W, v2);
-        if (!is_physical(W, v2, rho, p)) return -1;
-        P[0] = rho;
-        P[1] = p / (q.gam - 1.0);
-        velocity_out(q, G, W, v2, P);
-        return 0;
-    }
+    if (newton2d(q, tol, maxit, W, v2)) return finish_energy(q, G, W, v2, P) ? 0 : -1;
     if (!(q.D > 0.0)) return -2;
     const double lo = q.D;
     double hi = 2.0 * fmax(q.D, W0);
@@ -187,13 +204,7 @@ __device__ __forceinline__ int invert_energy(const Inv& q, const Geo& G, double 
     }
     if (!brent1d(q, 0, lo, hi, 0.0, &W)) return -2;
     v2 = v2_from_w(q, W);
-    const double rho = q.D * sqrt(1.0 - v2);
-    const double p = p_of_w(q, W, v2);
-    if (!is_physical(W, v2, rho, p)) return -2;
-    P[0] = rho;
-    P[1] = p / (q.gam - 1.0);
-    velocity_out(q, G, W, v2, P);
-    return 1;
+    return finish_energy(q, G, W, v2, P) ? 1 : -2;
 }
 
 __device__ __noinline__ int invert_entropy(const Inv& q, const Geo& G, double* P) {
@@ -206,8 +217,8 @@ __device__ __noinline__ int invert_entropy(const Inv& q, const Geo& G, double* P
     const double p = (q.ent / lor) * pow(rho, q.gam - 1.0);
     if (!is_physical(W, v2, rho, p)) return -1;
     P[0] = rho;
-    P[1] = p / (q.gam - 1.0);
-    velocity_out(q, G, W, v2, P);
+    P[1] = p * q.igam1;
+    velocity_out(q, G, W, lor, P);
     return 2;
 }
 
@@ -216,11 +227,10 @@ __device__ __noinline__ int invert_entropy(const Inv& q, const Geo& G, double* P
 __device__ __forceinline__ int invert_cell(const double* U, const double* Pg, const Geo& G, const RunDev& R,
                                            double* P) {
     Inv q;
-    inv_setup(U, G, R.gam, q);
-    const double ig = 1.0 / G.gdet;
-    P[5] = U[5] * ig;
-    P[6] = U[6] * ig;
-    P[7] = U[7] * ig;
+    inv_setup(U, G, R, q);
+    P[5] = U[5] * q.ig;
+    P[6] = U[6] * q.ig;
+    P[7] = U[7] * q.ig;
     St s;
     prim_state(Pg, G, R.gam, s);
     if (s.p < R.beta_ent * 0.5 * s.bsq) return invert_entropy(q, G, P);
@@ -242,7 +252,7 @@ __device__ __noinline__ void ceiling_reinvert(const RunDev& R, const Geo& G, dou
     U[0] += G.gdet * drho / G.alpha;
     U[1] -= G.gdet * (drho + du);
     Inv q;
-    inv_setup(U, G, R.gam, q);
+    inv_setup(U, G, R, q);
     const double W0 = s.lor * s.lor * s.w;
     const double qsq = s.lor * s.lor - 1.0;
     double Pn[NPR];

@@ -17,9 +17,10 @@ void launch_geometry(const GeoArgs& A, hipStream_t st);
 // bs: threads per workgroup (64, 128 or 256); sched bit 0: XCD-contiguous block order
 void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int bs, int sched,
                   hipStream_t st);
-// ent = 1 also computes and stores the entropy component (diagnostics); the stage chain uses 0
+// ent = 1 also computes and stores the entropy component (diagnostics); the stage chain uses 0.
+// uni = 1 (with ent = 0): the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int bs, int sched, hipStream_t st);
+                 int ent, int uni, int bs, int sched, hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
 // uni = 1: the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
 void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int uni, int bs,

@@ -211,6 +211,12 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
     const int64_t ci = cell_index(R, i, j, k);
     double* __restrict__ F = R.F[D];
+    Geo G;
+    if (UNI) {
+        // wave-uniform metric: read it ahead of any store of this kernel so that the loads are
+        // known not to be clobbered and become scalar loads
+        load_geo(D == 3 ? R.gc : R.gf[D], R.gpts, __builtin_amdgcn_readfirstlane((int)geo_index(R, i, j)), G);
+    }
     if (D == 2 && R.mks && (j == 0 || j == n2)) {
         if (ent_out) {
             *ent_out = 0.0;
@@ -236,13 +242,10 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         const double* Pq = P + q * R.vs;
         const double a = gld(Pq, (uint32_t)cm2), b = gld(Pq, (uint32_t)cm1), c = gld(Pq, (uint32_t)ci),
                      d = gld(Pq, (uint32_t)cp1);
-        Pl[q] = b + 0.5 * mc_slope(a, b, c);
-        Pr[q] = c - 0.5 * mc_slope(b, c, d);
+        Pl[q] = b + mc_half_slope(a, b, c);
+        Pr[q] = c - mc_half_slope(b, c, d);
     }
-    int64_t gi = geo_index(R, i, j);
-    if (UNI) gi = __builtin_amdgcn_readfirstlane((int)gi);
-    Geo G;
-    load_geo(D == 3 ? R.gc : R.gf[D], R.gpts, gi, G);
+    if (!UNI) load_geo(D == 3 ? R.gc : R.gf[D], R.gpts, geo_index(R, i, j), G);
     const double gam = R.gam;
     double Ul[NCS], Fl[NCS];
     double c1l, c2l;
@@ -296,7 +299,7 @@ __device__ __forceinline__ double entropy_flux(const RunDev& R, int i, int j, in
     return f;
 }
 
-template <int D, bool ENT>
+template <int D, bool ENT, bool UNI>
 __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                               int nruns, int which, int do_cfl, int sched) {
     const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -308,25 +311,34 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     const int j0 = D == 2 ? 0 : -R.act2;
     const int ni = D == 1 ? n1 + 1 : n1 + 2 * R.act1;
     const int nj = D == 2 ? n2 + 1 : n2 + 2 * R.act2;
-    const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
-    const int64_t total = (int64_t)ni * nj * n3;
+    // rows of n3 faces, ordered so that neighbouring rows along the stencil direction are
+    // consecutive (X1 faces: i fastest; X2 and X3 faces: j fastest).  Every index fits 31 bits
+    // (checked when a run is created); divisions use the run's precomputed multipliers.
+    const uint32_t nrows = (uint32_t)ni * (uint32_t)nj;
+    uint32_t row, k;
+    if (UNI) {
+        // n3 % 64 == 0: a wave is 64 consecutive k of one row, decomposed once per wave
+        const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)((uint32_t)(bl - boff[r]) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+        row = fdiv(wv, R.fd_kc);
+        k = ((wv - row * (uint32_t)(n3 >> 6)) << 6) + (threadIdx.x & 63);
+    } else {
+        const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
+        row = fdiv(e, R.fd_n3);
+        k = e - row * (uint32_t)n3;
+    }
     double cw = 0.0;
-    if (e < total) {
-        // rows of n3 faces, ordered so that neighbouring rows along the stencil direction are
-        // consecutive (X1 faces: i fastest; X2 and X3 faces: j fastest)
-        const int k = (int)(e % n3);
-        const int64_t t = e / n3;
+    if (row < nrows) {
+        const uint32_t q = fdiv(row, R.fd_row[D]);
         int i, j;
         if (D == 1) {
-            i = (int)(t % ni) + i0;
-            j = (int)(t / ni) + j0;
+            j = (int)q + j0;
+            i = (int)(row - q * (uint32_t)ni) + i0;
         } else {
-            j = (int)(t % nj) + j0;
-            i = (int)(t / nj) + i0;
+            i = (int)q + i0;
+            j = (int)(row - q * (uint32_t)nj) + j0;
         }
-        // one code path per kernel: keeping the scalar-metric variant beside the per-lane one costs
-        // ~30 VGPRs (3 instead of 4 waves per SIMD), more than the scalar loads save
-        cw = flux_face<D, false, ENT>(R, i, j, k, which, nullptr);
+        cw = flux_face<D, UNI, ENT>(R, i, j, (int)k, which, nullptr);
     }
     if (!do_cfl) return;
     __shared__ double red[4];
@@ -585,13 +597,8 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
 // the Lorentz cap.  Cells that need the entropy method (beta switch), Brent, or a magnetisation
 // ceiling go to the run's slow list and are finished by k_update_slow with the full procedure.
 template <bool UNI, int STAGE>
-__device__ __forceinline__ void update_fast(const RunDev& R, int64_t e) {
+__device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k) {
     constexpr int stage = STAGE;
-    const int n2 = R.n2, n3 = R.n3;
-    const int k = (int)(e % n3);
-    const int64_t t = e / n3;
-    const int j = (int)(t % n2);
-    const int i = (int)(t / n2);
     double U[NCS], Pg[NPR];
     Geo G;
     St sg;
@@ -601,23 +608,17 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int64_t e) {
     double P[NPR];
     if (!slow) {
         Inv q;
-        inv_setup(U, G, R.gam, q);
+        inv_setup(U, G, R, q);
         double W = sg.lor * sg.lor * sg.w;
         const double qsq = sg.lor * sg.lor - 1.0;
         double v2 = qsq / (1.0 + qsq);
         slow = !newton2d(q, R.c2p_tol, R.c2p_maxit, W, v2);
         if (!slow) {
-            const double rho = q.D * sqrt(1.0 - v2);
-            const double p = p_of_w(q, W, v2);
-            slow = !is_physical(W, v2, rho, p);
+            slow = !finish_energy(q, G, W, v2, P);
             if (!slow) {
-                P[0] = rho;
-                P[1] = p / (q.gam - 1.0);
-                velocity_out(q, G, W, v2, P);
-                const double ig = 1.0 / G.gdet;
-                P[5] = U[5] * ig;
-                P[6] = U[6] * ig;
-                P[7] = U[7] * ig;
+                P[5] = U[5] * q.ig;
+                P[6] = U[6] * q.ig;
+                P[7] = U[7] * q.ig;
                 P[0] = fmax(P[0], gld(R.gc + G_RHOFL * R.gpts, (uint32_t)gi));
                 P[1] = fmax(P[1], gld(R.gc + G_UFL * R.gpts, (uint32_t)gi));
                 St s;
@@ -634,7 +635,7 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int64_t e) {
     }
     if (slow) {
         const int pos = atomicAdd(&R.var->slow_count, 1);
-        R.slow_list[pos] = (int)e;
+        R.slow_list[pos] = (int)(((int64_t)i * R.n2 + j) * R.n3 + k);
         return;
     }
     const int64_t ci = cell_index(R, i, j, k);
@@ -654,9 +655,26 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
     const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
-    const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)R.n1 * R.n2 * R.n3) return;
-    update_fast<UNI, STAGE>(R, e);
+    if (UNI) {
+        // the blockDim/64 waves of a workgroup take consecutive i at the same (j, 64 k): the X1
+        // face fluxes and flux-CT neighbours shared by neighbouring i are read once per
+        // workgroup, not once per plane (rows of the run are padded to a multiple of the tile)
+        const uint32_t ti = blockDim.x >> 6;
+        const uint32_t eb = (uint32_t)(bl - boff[r]);
+        const uint32_t t = fdiv(eb, R.fd_kc);
+        const uint32_t kc = eb - t * (uint32_t)(R.n3 >> 6);
+        const uint32_t it = fdiv(t, R.fd_n2);
+        const int j = (int)(t - it * (uint32_t)R.n2);
+        const int i = (int)(it * ti) + (int)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        if (i >= R.n1) return;
+        update_fast<UNI, STAGE>(R, i, j, (int)(kc << 6) + (int)(threadIdx.x & 63));
+    } else {
+        const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
+        if (e >= (uint32_t)R.n1 * (uint32_t)R.n2 * (uint32_t)R.n3) return;
+        const uint32_t t = fdiv(e, R.fd_n3);
+        const uint32_t i = fdiv(t, R.fd_n2);
+        update_fast<UNI, STAGE>(R, (int)i, (int)(t - i * (uint32_t)R.n2), (int)(e - t * (uint32_t)R.n3));
+    }
 }
 
 // Slow path: the full inversion (beta switch, NR, Brent on W, entropy) and the full floors with
@@ -939,16 +957,20 @@ void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, i
 }
 
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int bs, int sched, hipStream_t st) {
+                 int ent, int uni, int bs, int sched, hipStream_t st) {
     if (nblocks <= 0) return;
     if (ent) {
-        if (d == 1) k_flux<1, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else if (d == 2) k_flux<2, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else k_flux<3, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        if (d == 1) k_flux<1, true, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else if (d == 2) k_flux<2, true, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else k_flux<3, true, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+    } else if (uni) {
+        if (d == 1) k_flux<1, false, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else if (d == 2) k_flux<2, false, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else k_flux<3, false, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
     } else {
-        if (d == 1) k_flux<1, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else if (d == 2) k_flux<2, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else k_flux<3, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        if (d == 1) k_flux<1, false, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else if (d == 2) k_flux<2, false, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else k_flux<3, false, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
     }
 }
 

@@ -128,6 +128,16 @@ def test_errors_are_reported_not_raised_in_c(G):
     assert ei.value.code == G.EINVAL
     with pytest.raises(G.GrmhdError):
         G.Context(c, make_torus(c), spin=1.5, r_in_grid=1.0)
+    # per-variable arrays beyond 4 GiB are refused before any input is read or memory is taken
+    import ctypes
+    L = G.load()
+    big = G.make_grid(c, n1=1020, n2=1020, n3=512)
+    out = ctypes.c_void_p()
+    dummy = np.zeros(8)
+    rc = L.grmhd_init(ctypes.byref(out), ctypes.byref(big), ctypes.byref(G.make_params(c)),
+                      dummy.ctypes.data, 0, None)
+    assert rc == G.EINVAL and not out.value
+    assert b"2^29" in L.grmhd_last_error()
 
 
 def test_autotuned_launch_shapes_give_identical_results(G):
