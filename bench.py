@@ -19,11 +19,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # algorithmic HBM bytes per unit processed by each kernel (state/flux traffic, FP64)
-#   flux_d : per face, the primitives of one cell (8 x 8 B) + the 8-component flux written (64 B)
-#   update : per cell, three face fluxes (3 x 64 B), P^n and the stage input (2 x 64 B), P_out (64 B),
-#            method code (1 B)
+#   flux_d : per face, the primitives of one cell (8 x 8 B) + the 7 stored flux slots written (56 B)
+#   update : per cell, its three lower faces' 7 flux slots (3 x 56 B), the stage input (64 B), P^n
+#            in stage 2 only (64 B; stage 1 shares the stage input), P_out (64 B), method code (1 B):
+#            297 B in stage 1, 361 B in stage 2, 329 B per launch on average
 #   bound  : per ghost cell, 8 primitives read and written
-ALG_BYTES = {"flux1": 128.0, "flux2": 128.0, "flux3": 128.0, "update": 385.0, "bound": 128.0}
+ALG_BYTES = {"flux1": 120.0, "flux2": 120.0, "flux3": 120.0, "update": 329.0, "bound": 128.0}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256.json")

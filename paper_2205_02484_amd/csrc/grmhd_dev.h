@@ -32,6 +32,18 @@ enum {
 };
 constexpr int NGF = G_IALPHA + 1;  // faces carry the entries up to 1/lapse
 
+// Stored face-flux slots.  The stage chain keeps 7 per face: the 5 fluid components and the two
+// field components transverse to the face (flux-CT builds the field update from those alone; the
+// flux of B^d through a d-face is never read).  Diagnostic copies also keep that normal field
+// component (slot 7) and the entropy component (slot 8); arrays are allocated with NCS slots.
+constexpr int NFS = 7;
+constexpr int FS_BN = 7, FS_ENT = 8;
+// slot of conserved component q < 8 in the X^D flux arrays (-1: the normal field component)
+template <int D>
+__host__ __device__ constexpr int flux_slot(int q) {
+    return q < 5 ? q : (q == 4 + D ? -1 : (q < 4 + D ? q : q - 1));
+}
+
 // Division of 0 <= n < 2^31 by a fixed d >= 1 with one high multiply, an add and a shift
 // (the round-up method of Granlund and Montgomery, "Division by invariant integers using
 // multiplication", 1994): l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1,

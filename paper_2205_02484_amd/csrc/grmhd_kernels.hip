@@ -200,6 +200,12 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Slot where flux_face stores component q (ENT: the diagnostic layout with every component).
+template <int D, bool ENT>
+__device__ __forceinline__ constexpr int flux_store_slot(int q) {
+    return q == NCS - 1 ? FS_ENT : (q == 4 + D ? FS_BN : flux_slot<D>(q));
+}
+
 // One face: returns c_w (0 when the face does not count for the CFL step).  The left state's
 // conserved vector, flux and speeds are finished before the right state is formed, which keeps
 // the live register set to one state plus two flux vectors.  With ENT = false the entropy
@@ -223,7 +229,8 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
             return 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) gst(F + q * R.vs, (uint32_t)ci, 0.0);
+        for (int q = 0; q < NQ; ++q)
+            if (ENT || q != 4 + D) gst(F + flux_store_slot<D, ENT>(q) * R.vs, (uint32_t)ci, 0.0);
         return 0.0;
     }
     const double* __restrict__ P = which ? R.Ph : R.P;
@@ -285,7 +292,10 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         return 0.0;
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) gst(F + q * R.vs, (uint32_t)ci, out[q]);
+    for (int q = 0; q < NQ; ++q) {
+        if (!ENT && q == 4 + D) continue;  // normal field component: not stored by the stage chain
+        gst(F + flux_store_slot<D, ENT>(q) * R.vs, (uint32_t)ci, out[q]);
+    }
     if (D != 1 && (i < 0 || i >= n1)) return 0.0;
     if (D != 2 && (j < 0 || j >= n2)) return 0.0;
     return cwf;
@@ -432,7 +442,6 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const double* __restrict__ F2 = R.F[2];
     const double* __restrict__ F3 = R.F[3];
     const bool has3 = R.act1 && R.act2, has1 = R.act2 && R.act3, has2 = R.act1 && R.act3;
-    constexpr int NQ = 8;   // the stored flux arrays carry no entropy component
 
     // ---- L = -sum_d (F_d(+) - F_d(-)) / dX^d with flux-CT for the field components ----
     double L[NCS];
@@ -451,46 +460,42 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
         const int64_t cp = ci + s1;
         if (R.act1) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (q >= 5 && q <= 7) continue;
+            for (int q = 0; q < 5; ++q)
                 L[q] -= (gld(F1 + q * vs, (uint32_t)cp) - gld(F1 + q * vs, (uint32_t)ci)) * R.idx[1];
-            }
         }
         if (R.act2) {
             const int64_t cq = ci + s2;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (q >= 5 && q <= 7) continue;
+            for (int q = 0; q < 5; ++q)
                 L[q] -= (gld(F2 + q * vs, (uint32_t)cq) - gld(F2 + q * vs, (uint32_t)ci)) * R.idx[2];
-            }
         }
         if (R.act3) {
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (q >= 5 && q <= 7) continue;
+            for (int q = 0; q < 5; ++q)
                 L[q] -= (gld(F3 + q * vs, (uint32_t)ckp) - gld(F3 + q * vs, (uint32_t)ci)) * R.idx[3];
-            }
         }
         // field components: F^d(B^d) = 0; transverse ones from edge EMFs where they exist
         double f1b2m = 0.0, f1b2p = 0.0, f1b3m = 0.0, f1b3p = 0.0;
         if (R.act1) {
-            f1b2m = gld(F1 + 6 * vs, (uint32_t)ci); f1b2p = gld(F1 + 6 * vs, (uint32_t)cp);
-            f1b3m = gld(F1 + 7 * vs, (uint32_t)ci); f1b3p = gld(F1 + 7 * vs, (uint32_t)cp);
+            f1b2m = gld(F1 + flux_slot<1>(6) * vs, (uint32_t)ci); f1b2p = gld(F1 + flux_slot<1>(6) * vs, (uint32_t)cp);
+            f1b3m = gld(F1 + flux_slot<1>(7) * vs, (uint32_t)ci); f1b3p = gld(F1 + flux_slot<1>(7) * vs, (uint32_t)cp);
         }
         double f2b1m = 0.0, f2b1p = 0.0, f2b3m = 0.0, f2b3p = 0.0;
         double f3b1m = 0.0, f3b1p = 0.0, f3b2m = 0.0, f3b2p = 0.0;
         if (R.act2) {
-            f2b1m = gld(F2 + 5 * vs, (uint32_t)ci); f2b1p = gld(F2 + 5 * vs, (uint32_t)(ci + s2));
-            f2b3m = gld(F2 + 7 * vs, (uint32_t)ci); f2b3p = gld(F2 + 7 * vs, (uint32_t)(ci + s2));
+            f2b1m = gld(F2 + flux_slot<2>(5) * vs, (uint32_t)ci);
+            f2b1p = gld(F2 + flux_slot<2>(5) * vs, (uint32_t)(ci + s2));
+            f2b3m = gld(F2 + flux_slot<2>(7) * vs, (uint32_t)ci);
+            f2b3p = gld(F2 + flux_slot<2>(7) * vs, (uint32_t)(ci + s2));
         }
         if (R.act3) {
-            f3b1m = gld(F3 + 5 * vs, (uint32_t)ci); f3b1p = gld(F3 + 5 * vs, (uint32_t)ckp);
-            f3b2m = gld(F3 + 6 * vs, (uint32_t)ci); f3b2p = gld(F3 + 6 * vs, (uint32_t)ckp);
+            f3b1m = gld(F3 + flux_slot<3>(5) * vs, (uint32_t)ci); f3b1p = gld(F3 + flux_slot<3>(5) * vs, (uint32_t)ckp);
+            f3b2m = gld(F3 + flux_slot<3>(6) * vs, (uint32_t)ci); f3b2p = gld(F3 + flux_slot<3>(6) * vs, (uint32_t)ckp);
         }
         if (has3) {
             // E3 at the four edges (i'-1/2, j'-1/2), i' in {i,i+1}, j' in {j,j+1}
-            const double* F1b2 = F1 + 6 * vs;
-            const double* F2b1 = F2 + 5 * vs;
+            const double* F1b2 = F1 + flux_slot<1>(6) * vs;
+            const double* F2b1 = F2 + flux_slot<2>(5) * vs;
             double E[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -509,8 +514,8 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
         }
         if (has1) {
             // E1 at edges (i, j'-1/2, k'-1/2)
-            const double* F2b3 = F2 + 7 * vs;
-            const double* F3b2 = F3 + 6 * vs;
+            const double* F2b3 = F2 + flux_slot<2>(7) * vs;
+            const double* F3b2 = F3 + flux_slot<3>(6) * vs;
             double E[2][2];
 #pragma unroll
             for (int b = 0; b < 2; ++b)
@@ -530,8 +535,8 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
         }
         if (has2) {
             // E2 at edges (i'-1/2, j, k'-1/2)
-            const double* F3b1 = F3 + 5 * vs;
-            const double* F1b3 = F1 + 7 * vs;
+            const double* F3b1 = F3 + flux_slot<3>(5) * vs;
+            const double* F1b3 = F1 + flux_slot<1>(7) * vs;
             double E[2][2];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -921,7 +926,8 @@ __global__ __launch_bounds__(256) void k_diag(RunDev R, int ih, double* __restri
     }
 }
 
-// copy raw fluxes of interior faces out in [9][m1][m2][m3] order
+// copy raw fluxes of interior faces out in [9][m1][m2][m3] order (diagnostic layout: every
+// component stored, by k_flux<d, true>)
 __global__ void k_flux_out(RunDev R, int d, double* __restrict__ out) {
     const int m1 = R.n1 + (d == 1), m2 = R.n2 + (d == 2), m3 = R.n3 + (d == 3);
     const int64_t n = (int64_t)m1 * m2 * m3;
@@ -931,7 +937,11 @@ __global__ void k_flux_out(RunDev R, int d, double* __restrict__ out) {
     const int64_t t = e / m3;
     const int j = (int)(t % m2), i = (int)(t / m2);
     const int64_t ci = cell_index(R, i, j, k % R.n3);
-    for (int q = 0; q < NCS; ++q) out[q * n + e] = R.F[d][q * R.vs + ci];
+    for (int q = 0; q < NCS; ++q) {
+        const int slot = d == 1 ? flux_store_slot<1, true>(q) : (d == 2 ? flux_store_slot<2, true>(q)
+                                                                        : flux_store_slot<3, true>(q));
+        out[q * n + e] = R.F[d][slot * R.vs + ci];
+    }
 }
 
 __global__ void k_set_var(RunVar* V, double dt_req, long long steps_left, int active) {
