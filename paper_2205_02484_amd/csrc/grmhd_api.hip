@@ -245,6 +245,7 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.fd_row[1] = make_fastdiv(g->n1 + 1);
     R.fd_row[2] = make_fastdiv(g->n2 + 1);
     R.fd_row[3] = make_fastdiv(g->n2 + 2 * R.act2);
+    for (int l = 0; l < 3; ++l) R.fd_jg[l] = make_fastdiv((g->n2 + (1 << l) - 1) >> l);
 
     auto bail = [&](int code) { free_run(r); return code; };
     if (hipMemsetAsync(r->mem, 0, L.total, st) != hipSuccess) return bail(fail(GRMHD_EDEVICE, "memset failed"));
@@ -351,8 +352,9 @@ struct Engine {
             case KB_F3: case KB_F3N:
                 return R.act3 && (kind == KB_F3) == (bool)R.geo_uniform ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3
                                                                          : 0;
-            // uniform-metric update: workgroups of bs/64 waves tile i, rows padded to that tile
-            case KB_UPD: return R.geo_uniform ? (n1 + bs / 64 - 1) / (bs / 64) * (bs / 64) * n2 * n3 : 0;
+            // uniform-metric update: workgroups of bs/64 waves on consecutive j (n2 padded to a
+            // multiple of that)
+            case KB_UPD: return R.geo_uniform ? n1 * ((n2 + bs / 64 - 1) / (bs / 64) * (bs / 64)) * n3 : 0;
             default: return R.geo_uniform ? 0 : n1 * n2 * n3;
         }
     }

@@ -64,6 +64,7 @@ struct RunDev {
     int32_t pad_;
     FastDiv fd_n2, fd_n3, fd_kc;  // divisors n2, n3, n3/64 (the last only when geo_uniform)
     FastDiv fd_row[4];          // [d]: row length of the flux-face rows: n1 + 1, n2 + 1, n2 + 2 act2
+    FastDiv fd_jg[3];           // [l]: number of j groups of 2^l rows, ceil(n2 / 2^l)
     int64_t s1, s2, vs;         // cell strides: i, j (k stride 1); variable stride
     int64_t gs1, gpts;          // geometry: i stride ((n2+4)), total points
     double dx[4], idx[4];

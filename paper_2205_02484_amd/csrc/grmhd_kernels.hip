@@ -425,12 +425,61 @@ __device__ __forceinline__ void source_terms(const St& s, const double* __restri
     S[3] = 0.0;
 }
 
+// X1-face data that a cell shares with its neighbour in i: the stored X1 flux slots of the face
+// at i' - 1/2 and the flux-CT EMFs on its edges, E3 at (i'-1/2, j+b-1/2) and E2 at
+// (i'-1/2, j, k+c-1/2) for b, c in {0, 1}.  The upper face of cell i is the lower face of i + 1.
+struct X1Face {
+    double f[NFS];
+    double e3[2], e2[2];
+};
+
+// Edge EMFs of flux-CT: the average of the four face fluxes of the transverse field around the
+// edge (Sec. 2.2).  E3 at (i'-1/2, j'-1/2) from cell index c of (i', j', k); zero on the axis.
+__device__ __forceinline__ double emf3(const RunDev& R, int64_t c, int jj) {
+    if (R.mks && (jj == 0 || jj == R.n2)) return 0.0;
+    const double* F1b2 = R.F[1] + flux_slot<1>(6) * R.vs;
+    const double* F2b1 = R.F[2] + flux_slot<2>(5) * R.vs;
+    return 0.25 * (gld(F1b2, (uint32_t)(c - R.s2)) + gld(F1b2, (uint32_t)c) - gld(F2b1, (uint32_t)(c - R.s1)) -
+                   gld(F2b1, (uint32_t)c));
+}
+// E2 at (i'-1/2, j, k'-1/2) from cell indices kk of (i', j, k') and kk1 of (i', j, k'-1)
+__device__ __forceinline__ double emf2(const RunDev& R, int64_t kk, int64_t kk1) {
+    const double* F3b1 = R.F[3] + flux_slot<3>(5) * R.vs;
+    const double* F1b3 = R.F[1] + flux_slot<1>(7) * R.vs;
+    return 0.25 * (gld(F3b1, (uint32_t)(kk - R.s1)) + gld(F3b1, (uint32_t)kk) - gld(F1b3, (uint32_t)kk1) -
+                   gld(F1b3, (uint32_t)kk));
+}
+
+// X1 face of cell index c (cell (i', j, k); cm, cp: its k-1 and k+1 neighbours)
+__device__ __forceinline__ void load_x1_face(const RunDev& R, int j, int64_t c, int64_t cm, int64_t cp, X1Face& x) {
+    if (!R.act1) return;
+    const double* __restrict__ F1 = R.F[1];
+#pragma unroll
+    for (int q = 0; q < NFS; ++q) x.f[q] = gld(F1 + q * R.vs, (uint32_t)c);
+    if (R.act2) {
+        x.e3[0] = emf3(R, c, j);
+        x.e3[1] = emf3(R, c + R.s2, j + 1);
+    }
+    if (R.act3) {
+        x.e2[0] = emf2(R, c, cm);
+        x.e2[1] = emf2(R, cp, c);
+    }
+}
+
+// lower X1 face of interior cell (i, j, k)
+__device__ __forceinline__ void x1_lower(const RunDev& R, int i, int j, int k, X1Face& x) {
+    const int64_t ci = cell_index(R, i, j, k);
+    const int64_t kb = ci - k;
+    load_x1_face(R, j, ci, kb + (k == 0 ? R.n3 - 1 : k - 1), kb + (k + 1 == R.n3 ? 0 : k + 1), x);
+}
+
 // Conserved state after the stage update of interior cell (i,j,k): flux-CT, the flux divergence,
 // the centred source from the stage-input primitives Pg, U = U(P^n) + c dt L.  With ENT = false
-// the entropy component (used only by the entropy inversion) is skipped.
+// the entropy component (used only by the entropy inversion) is skipped.  xf holds the cell's
+// lower X1 face on entry and its upper X1 face (the next cell's lower one) on return.
 template <bool ENT, bool UNI, int STAGE>
 __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k, double* U, double* Pg,
-                                            Geo& G, St& sg, int64_t& gi_out) {
+                                            Geo& G, St& sg, int64_t& gi_out, X1Face& xf) {
     constexpr int stage = STAGE;
     const int n2 = R.n2, n3 = R.n3;
     const int64_t ci = cell_index(R, i, j, k);
@@ -438,7 +487,6 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const int64_t kb = ci - k;
     const int64_t ckm = kb + (k == 0 ? n3 - 1 : k - 1);
     const int64_t ckp = kb + (k + 1 == n3 ? 0 : k + 1);
-    const double* __restrict__ F1 = R.F[1];
     const double* __restrict__ F2 = R.F[2];
     const double* __restrict__ F3 = R.F[3];
     const bool has3 = R.act1 && R.act2, has1 = R.act2 && R.act3, has2 = R.act1 && R.act3;
@@ -457,11 +505,11 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
         }
     }
     {
-        const int64_t cp = ci + s1;
+        X1Face up;
+        load_x1_face(R, j, ci + s1, ckm + s1, ckp + s1, up);
         if (R.act1) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q)
-                L[q] -= (gld(F1 + q * vs, (uint32_t)cp) - gld(F1 + q * vs, (uint32_t)ci)) * R.idx[1];
+            for (int q = 0; q < 5; ++q) L[q] -= (up.f[q] - xf.f[q]) * R.idx[1];
         }
         if (R.act2) {
             const int64_t cq = ci + s2;
@@ -474,11 +522,11 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
             for (int q = 0; q < 5; ++q)
                 L[q] -= (gld(F3 + q * vs, (uint32_t)ckp) - gld(F3 + q * vs, (uint32_t)ci)) * R.idx[3];
         }
-        // field components: F^d(B^d) = 0; transverse ones from edge EMFs where they exist
+        // field components: F^d(B^d) is not used; transverse ones from edge EMFs where they exist
         double f1b2m = 0.0, f1b2p = 0.0, f1b3m = 0.0, f1b3p = 0.0;
         if (R.act1) {
-            f1b2m = gld(F1 + flux_slot<1>(6) * vs, (uint32_t)ci); f1b2p = gld(F1 + flux_slot<1>(6) * vs, (uint32_t)cp);
-            f1b3m = gld(F1 + flux_slot<1>(7) * vs, (uint32_t)ci); f1b3p = gld(F1 + flux_slot<1>(7) * vs, (uint32_t)cp);
+            f1b2m = xf.f[flux_slot<1>(6)]; f1b2p = up.f[flux_slot<1>(6)];
+            f1b3m = xf.f[flux_slot<1>(7)]; f1b3p = up.f[flux_slot<1>(7)];
         }
         double f2b1m = 0.0, f2b1p = 0.0, f2b3m = 0.0, f2b3p = 0.0;
         double f3b1m = 0.0, f3b1p = 0.0, f3b2m = 0.0, f3b2p = 0.0;
@@ -493,24 +541,11 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
             f3b2m = gld(F3 + flux_slot<3>(6) * vs, (uint32_t)ci); f3b2p = gld(F3 + flux_slot<3>(6) * vs, (uint32_t)ckp);
         }
         if (has3) {
-            // E3 at the four edges (i'-1/2, j'-1/2), i' in {i,i+1}, j' in {j,j+1}
-            const double* F1b2 = F1 + flux_slot<1>(6) * vs;
-            const double* F2b1 = F2 + flux_slot<2>(5) * vs;
-            double E[2][2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int jj = j + b;
-                    if (R.mks && (jj == 0 || jj == n2)) { E[a][b] = 0.0; continue; }
-                    const int64_t c = ci + a * s1 + b * s2;
-                    E[a][b] = 0.25 * (gld(F1b2, (uint32_t)(c - s2)) + gld(F1b2, (uint32_t)c) -
-                                      gld(F2b1, (uint32_t)(c - s1)) - gld(F2b1, (uint32_t)c));
-                }
-            f1b2m = 0.5 * (E[0][0] + E[0][1]);
-            f1b2p = 0.5 * (E[1][0] + E[1][1]);
-            f2b1m = -0.5 * (E[0][0] + E[1][0]);
-            f2b1p = -0.5 * (E[0][1] + E[1][1]);
+            // E3 on the four edges (i'-1/2, j'-1/2), i' in {i, i+1}, j' in {j, j+1}
+            f1b2m = 0.5 * (xf.e3[0] + xf.e3[1]);
+            f1b2p = 0.5 * (up.e3[0] + up.e3[1]);
+            f2b1m = -0.5 * (xf.e3[0] + up.e3[0]);
+            f2b1p = -0.5 * (xf.e3[1] + up.e3[1]);
         }
         if (has1) {
             // E1 at edges (i, j'-1/2, k'-1/2)
@@ -534,23 +569,11 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
             f3b2p = -0.5 * (E[0][1] + E[1][1]);
         }
         if (has2) {
-            // E2 at edges (i'-1/2, j, k'-1/2)
-            const double* F3b1 = F3 + flux_slot<3>(5) * vs;
-            const double* F1b3 = F1 + flux_slot<1>(7) * vs;
-            double E[2][2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int64_t kk = c == 0 ? ci : ckp;
-                    const int64_t kk1 = c == 0 ? ckm : ci;
-                    E[a][c] = 0.25 * (gld(F3b1, (uint32_t)(kk + (a - 1) * s1)) + gld(F3b1, (uint32_t)(kk + a * s1)) -
-                                      gld(F1b3, (uint32_t)(kk1 + a * s1)) - gld(F1b3, (uint32_t)(kk + a * s1)));
-                }
-            f1b3m = -0.5 * (E[0][0] + E[0][1]);
-            f1b3p = -0.5 * (E[1][0] + E[1][1]);
-            f3b1m = 0.5 * (E[0][0] + E[1][0]);
-            f3b1p = 0.5 * (E[0][1] + E[1][1]);
+            // E2 on the edges (i'-1/2, j, k'-1/2), i' in {i, i+1}, k' in {k, k+1}
+            f1b3m = -0.5 * (xf.e2[0] + xf.e2[1]);
+            f1b3p = -0.5 * (up.e2[0] + up.e2[1]);
+            f3b1m = 0.5 * (xf.e2[0] + up.e2[0]);
+            f3b1p = 0.5 * (xf.e2[1] + up.e2[1]);
         }
         if (R.act1) {
             L[6] -= (f1b2p - f1b2m) * R.idx[1];
@@ -564,6 +587,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
             L[5] -= (f3b1p - f3b1m) * R.idx[3];
             L[6] -= (f3b2p - f3b2m) * R.idx[3];
         }
+        xf = up;
     }
 
     int64_t gi = geo_index(R, i, j);
@@ -602,13 +626,13 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
 // the Lorentz cap.  Cells that need the entropy method (beta switch), Brent, or a magnetisation
 // ceiling go to the run's slow list and are finished by k_update_slow with the full procedure.
 template <bool UNI, int STAGE>
-__device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k) {
+__device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k, X1Face& xf) {
     constexpr int stage = STAGE;
     double U[NCS], Pg[NPR];
     Geo G;
     St sg;
     int64_t gi;
-    stage_state<false, UNI, STAGE>(R, i, j, k, U, Pg, G, sg, gi);
+    stage_state<false, UNI, STAGE>(R, i, j, k, U, Pg, G, sg, gi, xf);
     bool slow = sg.p < R.beta_ent * 0.5 * sg.bsq;
     double P[NPR];
     if (!slow) {
@@ -661,24 +685,30 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
     const RunDev& R = runs[r];
     if (!R.var->active) return;
     if (UNI) {
-        // the blockDim/64 waves of a workgroup take consecutive i at the same (j, 64 k): the X1
-        // face fluxes and flux-CT neighbours shared by neighbouring i are read once per
-        // workgroup, not once per plane (rows of the run are padded to a multiple of the tile)
-        const uint32_t ti = blockDim.x >> 6;
+        // The blockDim/64 waves of a workgroup take consecutive j at the same (i, 64 k), so the X2
+        // faces and flux-CT neighbours they share are fetched together.  Block order: 64-k chunk
+        // fastest, then j group, then i (n2 padded to a multiple of the group).
+        const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const uint32_t lw = blockDim.x == 256 ? 2u : (blockDim.x == 128 ? 1u : 0u);
         const uint32_t eb = (uint32_t)(bl - boff[r]);
         const uint32_t t = fdiv(eb, R.fd_kc);
         const uint32_t kc = eb - t * (uint32_t)(R.n3 >> 6);
-        const uint32_t it = fdiv(t, R.fd_n2);
-        const int j = (int)(t - it * (uint32_t)R.n2);
-        const int i = (int)(it * ti) + (int)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        if (i >= R.n1) return;
-        update_fast<UNI, STAGE>(R, i, j, (int)(kc << 6) + (int)(threadIdx.x & 63));
+        const uint32_t i = fdiv(t, R.fd_jg[lw]);
+        const int j = (int)(((t - i * (uint32_t)((R.n2 + (1 << lw) - 1) >> lw)) << lw) + wv);
+        if (j >= R.n2) return;
+        const int k = (int)(kc << 6) + (int)(threadIdx.x & 63);
+        X1Face xf;
+        x1_lower(R, (int)i, j, k, xf);
+        update_fast<UNI, STAGE>(R, (int)i, j, k, xf);
     } else {
         const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
         if (e >= (uint32_t)R.n1 * (uint32_t)R.n2 * (uint32_t)R.n3) return;
         const uint32_t t = fdiv(e, R.fd_n3);
         const uint32_t i = fdiv(t, R.fd_n2);
-        update_fast<UNI, STAGE>(R, (int)i, (int)(t - i * (uint32_t)R.n2), (int)(e - t * (uint32_t)R.n3));
+        const int j = (int)(t - i * (uint32_t)R.n2), k = (int)(e - t * (uint32_t)R.n3);
+        X1Face xf;
+        x1_lower(R, (int)i, j, k, xf);
+        update_fast<UNI, STAGE>(R, (int)i, j, k, xf);
     }
 }
 
@@ -699,8 +729,10 @@ __global__ __launch_bounds__(256) void k_update_slow(const RunDev* __restrict__ 
         Geo G;
         St sg;
         int64_t gi;
-        if (stage == 1) stage_state<true, false, 1>(R, i, j, k, U, Pg, G, sg, gi);
-        else stage_state<true, false, 2>(R, i, j, k, U, Pg, G, sg, gi);
+        X1Face xf;
+        x1_lower(R, i, j, k, xf);
+        if (stage == 1) stage_state<true, false, 1>(R, i, j, k, U, Pg, G, sg, gi, xf);
+        else stage_state<true, false, 2>(R, i, j, k, U, Pg, G, sg, gi, xf);
         double P[NPR];
 #pragma unroll
         for (int q = 0; q < NPR; ++q) P[q] = Pg[q];
