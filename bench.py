@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="torus3d_256x256x256")
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps in the CPU-baseline sample")
+    ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble and served-stream legs")
     ap.add_argument("--ensemble-steps", type=int, default=500, help="steps of each of the 48 ensemble tori")
