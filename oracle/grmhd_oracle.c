@@ -24,6 +24,9 @@
  *   floors, magnetisation ceilings, Lorentz cap                Sec. 2.4 (Flooring model)
  *   Kerr-Schild metric, MKS coordinates, boundary conditions   Sec. 4.1
  *   horizon mass accretion rate and magnetic flux              Sec. 4.2, Eqs. diag_Mdot, diag_MAD
+ *   angular momentum and energy fluxes, radial profiles of the
+ *   mass flux and of the inward/outward angular momentum flux  Sec. 4.2, Eqs.
+ *                                       angular_momentum_horizon, energy_flux_horizon, lin, lout
  *
  * Where the text is garbled or silent the code takes one reading, marked READING-n at the place
  * it is used:
@@ -1165,6 +1168,60 @@ int orc_diag(const orc_cfg* c, const double* Pint, double* mdot, double* phib) {
             }
     *mdot = m;
     *phib = f;
+    work_free(&w);
+    return ih;
+}
+
+/* Accretion diagnostics of Sec. 4.2 (READING-19 for the horizon shell).  For every radial cell i,
+ * summed over its (j, k) shell with weight dX2 dX3:
+ *   rad[0][i] = sum sqrt(-g) rho u^1                (mass flux, Eq. diag_Mdot at r_i)
+ *   rad[1][i] = 1/2 sum sqrt(-g) |B^1|              (Eq. diag_MAD)
+ *   rad[2][i] = sum sqrt(-g) T^1_3                  (angular momentum flux, Eq. angular_momentum_horizon)
+ *   rad[3][i] = -sum sqrt(-g) T^1_0                 (energy flux, Eq. energy_flux_horizon)
+ *   rad[4][i] = sum sqrt(-g) (rho + u + p + b^2) u^1 u_3 / rad[0][i]   (Eq. lin)
+ *   rad[5][i] = sum sqrt(-g) b^1 b_3 / rad[0][i]                      (Eq. lout)
+ * The MKS sums equal the paper's theta-phi integrals: sqrt(-g_MKS) dX2 carries dtheta/dX2 and
+ * dr/dX1, and the X1 components carry dX1/dr.  rad[4], rad[5] are NaN where rad[0] is 0.
+ * hz = (Mdot, phi_B, Ldot, Edot, phi_B / sqrt|Mdot|) of the first cell with r >= r_h, whose
+ * index is returned (-1 if the grid does not reach it; hz untouched then). */
+int orc_diag_full(const orc_cfg* c, const double* Pint, double* hz, double* rad) {
+    if (c->coords != ORC_MKS) return -1;
+    Work w;
+    int rc = work_init(&w, c);
+    if (rc) { work_free(&w); return rc; }
+    load_interior(&w.g, Pint, w.Pn);
+    const int n1 = c->n1;
+    const double dA = w.g.dx[2] * w.g.dx[3];
+    for (int i = 0; i < n1; i++) {
+        double s[6] = {0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < c->n2; j++)
+            for (int k = 0; k < c->n3; k++) {
+                const Geom* G = &w.g.gc[gidx(&w.g, i, j)];
+                const double* P = &w.Pn[cidx(&w.g, i, j, k) * NPR];
+                State S;
+                get_state(P, G, c->gam, &S);
+                s[0] += G->gdet * P[0] * S.ucon[1] * dA;
+                s[1] += 0.5 * G->gdet * fabs(P[5]) * dA;
+                s[2] += G->gdet * tmix(&S, 1, 3) * dA;
+                s[3] += -G->gdet * tmix(&S, 1, 0) * dA;
+                s[4] += G->gdet * (S.w + S.bsq) * S.ucon[1] * S.ucov[3] * dA;
+                s[5] += G->gdet * S.bcon[1] * S.bcov[3] * dA;
+            }
+        rad[0 * n1 + i] = s[0];
+        rad[1 * n1 + i] = s[1];
+        rad[2 * n1 + i] = s[2];
+        rad[3 * n1 + i] = s[3];
+        rad[4 * n1 + i] = s[0] != 0.0 ? s[4] / s[0] : NAN;
+        rad[5 * n1 + i] = s[0] != 0.0 ? s[5] / s[0] : NAN;
+    }
+    double rh = 1.0 + sqrt(1.0 - c->a * c->a);
+    int ih = -1;
+    for (int i = 0; i < n1; i++)
+        if (w.g.gc[gidx(&w.g, i, 0)].r >= rh) { ih = i; break; }
+    if (ih >= 0) {
+        for (int q = 0; q < 4; q++) hz[q] = rad[q * n1 + ih];
+        hz[4] = hz[0] != 0.0 ? hz[1] / sqrt(fabs(hz[0])) : 0.0;
+    }
     work_free(&w);
     return ih;
 }
