@@ -109,6 +109,27 @@ int grmhd_prim2cons(grmhd_ctx* ctx, const double* P, double* U, int32_t on_devic
  * phi_b = 1/2 sum sqrt(-g) |B^1| dX2 dX3 on the first radial cell with r >= r_horizon.  MKS only. */
 int grmhd_diag(grmhd_ctx* ctx, double* mdot, double* phi_b);
 
+/* Accretion diagnostics of the current state on the horizon shell (Sec. 4.2, Eqs. diag_Mdot,
+ * diag_MAD, angular_momentum_horizon, energy_flux_horizon and the MAD parameter), each a sum over
+ * the (j, k) cells of the first radial index whose centre has r >= r_horizon, weighted by
+ * dX2 dX3 (the MKS sums equal the paper's theta-phi integrals).  MKS only. */
+typedef struct {
+    double mdot;        /* sum sqrt(-g) rho u^1 (signed: negative for inflow) */
+    double phi_b;       /* 1/2 sum sqrt(-g) |B^1| */
+    double ldot;        /* sum sqrt(-g) T^1_3 */
+    double edot;        /* -sum sqrt(-g) T^1_0 */
+    double phi_b_norm;  /* phi_b / sqrt(|mdot|), 0 when mdot is 0 */
+    int32_t i_h;        /* radial index of the horizon shell */
+    int32_t reserved_;
+} grmhd_horizon;
+
+/* Fills *hz and, when `radial` is non-NULL, the radial profiles radial[6][n1] (host, caller-owned):
+ * rows 0-3 the four shell sums above for every radial index i, row 4 the inward angular-momentum
+ * flux sum sqrt(-g)(rho + u + p + b^2) u^1 u_3 / row 0 (Eq. lin), row 5 the outward one
+ * sum sqrt(-g) b^1 b_3 / row 0 (Eq. lout); rows 4-5 are NaN where row 0 is 0.  Waits for the
+ * context's stream.  EINVAL for a non-MKS grid or one that does not reach the horizon. */
+int grmhd_diag_full(grmhd_ctx* ctx, grmhd_horizon* hz, double* radial);
+
 /* Copy the current primitive fields out ([8][n1][n2][n3]). */
 int grmhd_get_prims(grmhd_ctx* ctx, double* out, int32_t out_on_device);
 

@@ -1172,6 +1172,45 @@ int orc_diag(const orc_cfg* c, const double* Pint, double* mdot, double* phib) {
     return ih;
 }
 
+/* Magnitude state: the 4-vectors of get_state evaluated with every operand replaced by its
+ * magnitude (u^i from |u~^i| + Gamma |beta^i| / alpha, lowering with |g_mu nu|, and so on).  A
+ * quantity built from these bounds the size of the partial results that form it, so
+ * eps x (magnitude) bounds its rounding error to first order: the scale for comparing two
+ * evaluations of a quantity that cancels (u^1 of a flow nearly at rest in the Kerr-Schild frame). */
+static void get_state_mag(const double* P, const Geom* G, double gam, const State* S, State* M) {
+    const double alpha = G->alpha, lor = S->lor;
+    M->ucon[0] = S->ucon[0];
+    for (int i = 1; i < 4; i++) M->ucon[i] = fabs(P[1 + i]) + lor * alpha * fabs(G->gcon[0][i]);
+    for (int m = 0; m < 4; m++) {
+        double acc = 0.0;
+        for (int n = 0; n < 4; n++) acc += fabs(G->gcov[m][n]) * M->ucon[n];
+        M->ucov[m] = acc;
+    }
+    double bt = 0.0;
+    for (int i = 1; i < 4; i++) bt += fabs(P[4 + i]) * M->ucov[i];
+    M->bcon[0] = bt;
+    for (int i = 1; i < 4; i++) M->bcon[i] = (fabs(P[4 + i]) + bt * M->ucon[i]) / S->ucon[0];
+    for (int m = 0; m < 4; m++) {
+        double acc = 0.0;
+        for (int n = 0; n < 4; n++) acc += fabs(G->gcov[m][n]) * M->bcon[n];
+        M->bcov[m] = acc;
+    }
+    double bsq = 0.0;
+    for (int m = 0; m < 4; m++) bsq += M->bcon[m] * M->bcov[m];
+    M->bsq = bsq;
+    M->rho = fabs(P[0]);
+    M->u = fabs(P[1]);
+    M->p = fabs((gam - 1.0) * P[1]);
+    M->w = M->rho + M->u + M->p;
+    M->lor = lor;
+}
+
+/* magnitude counterpart of tmix */
+static double tmix_mag(const State* M, int m, int n) {
+    return (M->w + M->bsq) * M->ucon[m] * M->ucov[n] + (m == n ? M->p + 0.5 * M->bsq : 0.0) +
+           M->bcon[m] * M->bcov[n];
+}
+
 /* Accretion diagnostics of Sec. 4.2 (READING-19 for the horizon shell).  For every radial cell i,
  * summed over its (j, k) shell with weight dX2 dX3:
  *   rad[0][i] = sum sqrt(-g) rho u^1                (mass flux, Eq. diag_Mdot at r_i)
@@ -1183,8 +1222,11 @@ int orc_diag(const orc_cfg* c, const double* Pint, double* mdot, double* phib) {
  * The MKS sums equal the paper's theta-phi integrals: sqrt(-g_MKS) dX2 carries dtheta/dX2 and
  * dr/dX1, and the X1 components carry dX1/dr.  rad[4], rad[5] are NaN where rad[0] is 0.
  * hz = (Mdot, phi_B, Ldot, Edot, phi_B / sqrt|Mdot|) of the first cell with r >= r_h, whose
- * index is returned (-1 if the grid does not reach it; hz untouched then). */
-int orc_diag_full(const orc_cfg* c, const double* Pint, double* hz, double* rad) {
+ * index is returned (-1 if the grid does not reach it; hz untouched then).  absum (nullable,
+ * [6][n1]) receives, per shell, the sum of the terms evaluated on the magnitude state (rows 4, 5:
+ * of the numerators): eps times it bounds, to first order, the rounding of each signed sum,
+ * including the cancellation inside every term. */
+int orc_diag_full(const orc_cfg* c, const double* Pint, double* hz, double* rad, double* absum) {
     if (c->coords != ORC_MKS) return -1;
     Work w;
     int rc = work_init(&w, c);
@@ -1193,20 +1235,35 @@ int orc_diag_full(const orc_cfg* c, const double* Pint, double* hz, double* rad)
     const int n1 = c->n1;
     const double dA = w.g.dx[2] * w.g.dx[3];
     for (int i = 0; i < n1; i++) {
-        double s[6] = {0, 0, 0, 0, 0, 0};
+        double s[6] = {0, 0, 0, 0, 0, 0}, a[6] = {0, 0, 0, 0, 0, 0};
         for (int j = 0; j < c->n2; j++)
             for (int k = 0; k < c->n3; k++) {
                 const Geom* G = &w.g.gc[gidx(&w.g, i, j)];
                 const double* P = &w.Pn[cidx(&w.g, i, j, k) * NPR];
                 State S;
                 get_state(P, G, c->gam, &S);
-                s[0] += G->gdet * P[0] * S.ucon[1] * dA;
-                s[1] += 0.5 * G->gdet * fabs(P[5]) * dA;
-                s[2] += G->gdet * tmix(&S, 1, 3) * dA;
-                s[3] += -G->gdet * tmix(&S, 1, 0) * dA;
-                s[4] += G->gdet * (S.w + S.bsq) * S.ucon[1] * S.ucov[3] * dA;
-                s[5] += G->gdet * S.bcon[1] * S.bcov[3] * dA;
+                State M;
+                get_state_mag(P, G, c->gam, &S, &M);
+                double t[6], tm[6];
+                t[0] = G->gdet * P[0] * S.ucon[1] * dA;
+                t[1] = 0.5 * G->gdet * fabs(P[5]) * dA;
+                t[2] = G->gdet * tmix(&S, 1, 3) * dA;
+                t[3] = -G->gdet * tmix(&S, 1, 0) * dA;
+                t[4] = G->gdet * (S.w + S.bsq) * S.ucon[1] * S.ucov[3] * dA;
+                t[5] = G->gdet * S.bcon[1] * S.bcov[3] * dA;
+                tm[0] = G->gdet * M.rho * M.ucon[1] * dA;
+                tm[1] = fabs(t[1]);
+                tm[2] = G->gdet * tmix_mag(&M, 1, 3) * dA;
+                tm[3] = G->gdet * tmix_mag(&M, 1, 0) * dA;
+                tm[4] = G->gdet * (M.w + M.bsq) * M.ucon[1] * M.ucov[3] * dA;
+                tm[5] = G->gdet * M.bcon[1] * M.bcov[3] * dA;
+                for (int q = 0; q < 6; q++) {
+                    s[q] += t[q];
+                    a[q] += tm[q];
+                }
             }
+        if (absum)
+            for (int q = 0; q < 6; q++) absum[q * n1 + i] = a[q];
         rad[0 * n1 + i] = s[0];
         rad[1 * n1 + i] = s[1];
         rad[2 * n1 + i] = s[2];

@@ -63,7 +63,7 @@ def lib():
         L.orc_prim2cons.argtypes = [cp, dp, dp]
         L.orc_cons2prim.argtypes = [cp, dp, dp, bp]
         L.orc_diag.argtypes = [cp, dp, dp, dp]
-        L.orc_diag_full.argtypes = [cp, dp, dp, dp]
+        L.orc_diag_full.argtypes = [cp, dp, dp, dp, dp]
         L.orc_geom.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.orc_point_state.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp] + [dp] * 10
         L.orc_point_c2p.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
@@ -188,13 +188,17 @@ def diag(cfg: OrcCfg, P):
     return m.value, f.value, ih
 
 
-def diag_full(cfg: OrcCfg, P):
+def diag_full(cfg: OrcCfg, P, with_absum: bool = False):
     """Horizon (Mdot, phi_B, Ldot, Edot, Phi_B), the radial profiles [6][n1] (Mdot, phi_B, Ldot,
-    Edot, ldot_in, ldot_out per radial cell) and the horizon index."""
+    Edot, ldot_in, ldot_out per radial cell) and the horizon index; with_absum also returns the
+    per-shell sums of the magnitudes of the terms (the rounding scale of each signed sum)."""
     P = _arr(P, (8, cfg.n1, cfg.n2, cfg.n3))
     hz = np.full(5, np.nan)
     rad = np.empty((6, cfg.n1))
-    ih = lib().orc_diag_full(ctypes.byref(cfg), _dp(P), _dp(hz), _dp(rad))
+    ab = np.empty((6, cfg.n1))
+    ih = lib().orc_diag_full(ctypes.byref(cfg), _dp(P), _dp(hz), _dp(rad), _dp(ab))
+    if with_absum:
+        return hz, rad, ih, ab
     return hz, rad, ih
 
 

@@ -719,6 +719,40 @@ int grmhd_diag(grmhd_ctx* c, double* mdot, double* phi_b) {
     return GRMHD_OK;
 }
 
+int grmhd_diag_full(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
+    if (!c || !hz) return fail(GRMHD_EINVAL, "NULL argument");
+    const RunDev& R = c->run->h;
+    if (!R.mks || c->run->ih < 0) return fail(GRMHD_EINVAL, "diagnostics need an MKS grid reaching the horizon");
+    const int n1 = R.n1;
+    double* d = nullptr;
+    HIPCHK(hipMalloc(&d, 6 * (size_t)n1 * sizeof(double)));
+    std::vector<double> h(6 * (size_t)n1);
+    launch_diag_shells(R, d, c->eng.st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->eng.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->eng.st);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "diag_full: %s", hipGetErrorString(e));
+    const int ih = c->run->ih;
+    hz->mdot = h[0 * n1 + ih];
+    hz->phi_b = h[1 * n1 + ih];
+    hz->ldot = h[2 * n1 + ih];
+    hz->edot = h[3 * n1 + ih];
+    hz->phi_b_norm = hz->mdot != 0.0 ? hz->phi_b / std::sqrt(std::fabs(hz->mdot)) : 0.0;
+    hz->i_h = ih;
+    hz->reserved_ = 0;
+    if (radial) {
+        for (int q = 0; q < 4; ++q)
+            for (int i = 0; i < n1; ++i) radial[q * n1 + i] = h[q * n1 + i];
+        for (int i = 0; i < n1; ++i) {
+            const double m = h[i];
+            radial[4 * n1 + i] = m != 0.0 ? h[4 * n1 + i] / m : NAN;
+            radial[5 * n1 + i] = m != 0.0 ? h[5 * n1 + i] / m : NAN;
+        }
+    }
+    return GRMHD_OK;
+}
+
 static int get_prims_run(Run* r, hipStream_t st, double* out, int32_t out_on_device) {
     const RunDev& R = r->h;
     const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;

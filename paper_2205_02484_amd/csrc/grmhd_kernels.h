@@ -32,6 +32,8 @@ void launch_store(const RunDev& R, double* out, const int8_t* code_in, int8_t* c
 void launch_prim2cons(const RunDev& R, const double* P, double* U, hipStream_t st);
 void launch_cons2prim(const RunDev& R, const double* U, double* P, int8_t* code, hipStream_t st);
 void launch_diag(const RunDev& R, int ih, double* out, hipStream_t st);
+// per radial shell: the six accretion sums of Sec. 4.2, out[6][n1] (device)
+void launch_diag_shells(const RunDev& R, double* out, hipStream_t st);
 void launch_flux_out(const RunDev& R, int d, double* out, hipStream_t st);
 void launch_set_var(RunVar* V, double dt_req, long long steps_left, int active, hipStream_t st);
 

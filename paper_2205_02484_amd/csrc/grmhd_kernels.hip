@@ -958,6 +958,45 @@ __global__ __launch_bounds__(256) void k_diag(RunDev R, int ih, double* __restri
     }
 }
 
+// Accretion diagnostics (Sec. 4.2) of every radial shell: workgroup i sums over the (j, k) cells
+// of radial index i, each term weighted by dX2 dX3, in a fixed order (strided partial sums, then a
+// tree), out[q * n1 + i] for q = 0..5:
+//   sqrt(-g) rho u^1, 1/2 sqrt(-g) |B^1|, sqrt(-g) T^1_3, -sqrt(-g) T^1_0,
+//   sqrt(-g) (rho + u + p + b^2) u^1 u_3, sqrt(-g) b^1 b_3
+__global__ __launch_bounds__(256) void k_diag_shells(RunDev R, double* __restrict__ out) {
+    __shared__ double sm[6][256];
+    const int i = blockIdx.x;
+    const int n2 = R.n2, n3 = R.n3;
+    const double dA = R.dx[2] * R.dx[3];
+    double a[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < n2 * n3; e += 256) {
+        const int j = e / n3, k = e % n3;
+        Geo G;
+        load_geo(R.gc, R.gpts, geo_index(R, i, j), G);
+        const int64_t ci = cell_index(R, i, j, k);
+        double P[NPR];
+        for (int q = 0; q < NPR; ++q) P[q] = R.P[q * R.vs + ci];
+        St st;
+        prim_state(P, G, R.gam, st);
+        double F[NCS];
+        flux_of<1>(P, st, G, 0.0, F);  // F[1..4] = sqrt(-g) T^1_nu
+        a[0] += G.gdet * P[0] * st.u1 * R.dx[2] * R.dx[3];
+        a[1] += 0.5 * G.gdet * fabs(P[5]) * R.dx[2] * R.dx[3];
+        a[2] += F[4] * dA;
+        a[3] += -F[1] * dA;
+        a[4] += G.gdet * (st.w + st.bsq) * st.u1 * st.l3 * dA;
+        a[5] += G.gdet * st.b1 * st.c3 * dA;
+    }
+    for (int q = 0; q < 6; ++q) sm[q][threadIdx.x] = a[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 6; ++q) sm[q][threadIdx.x] += sm[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x * R.n1 + i] = sm[threadIdx.x][0];
+}
+
 // copy raw fluxes of interior faces out in [9][m1][m2][m3] order (diagnostic layout: every
 // component stored, by k_flux<d, true>)
 __global__ void k_flux_out(RunDev R, int d, double* __restrict__ out) {
@@ -1056,6 +1095,9 @@ void launch_cons2prim(const RunDev& R, const double* U, double* P, int8_t* code,
 }
 void launch_diag(const RunDev& R, int ih, double* out, hipStream_t st) {
     k_diag<<<1, 256, 0, st>>>(R, ih, out);
+}
+void launch_diag_shells(const RunDev& R, double* out, hipStream_t st) {
+    k_diag_shells<<<R.n1, 256, 0, st>>>(R, out);
 }
 void launch_flux_out(const RunDev& R, int d, double* out, hipStream_t st) {
     const int64_t n = (int64_t)(R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));

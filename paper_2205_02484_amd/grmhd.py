@@ -23,7 +23,7 @@ LLF, HLL = 0, 1
 # exported symbols of include/grmhd.h
 SYMBOLS = [
     "grmhd_params_default", "grmhd_init", "grmhd_step", "grmhd_steps", "grmhd_cons2prim",
-    "grmhd_prim2cons", "grmhd_diag", "grmhd_get_prims", "grmhd_get_time", "grmhd_get_codes",
+    "grmhd_prim2cons", "grmhd_diag", "grmhd_diag_full", "grmhd_get_prims", "grmhd_get_time", "grmhd_get_codes",
     "grmhd_debug_fluxes", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
     "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_autotune", "grmhd_batch_poll",
     "grmhd_batch_fetch", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
@@ -34,6 +34,12 @@ class Grid(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
                 ("coords", ctypes.c_int32), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
                 ("h", ctypes.c_double), ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3)]
+
+
+class Horizon(ctypes.Structure):
+    _fields_ = [("mdot", ctypes.c_double), ("phi_b", ctypes.c_double), ("ldot", ctypes.c_double),
+                ("edot", ctypes.c_double), ("phi_b_norm", ctypes.c_double), ("i_h", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -75,6 +81,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_cons2prim.argtypes = [vp, vp, vp, vp, i32]
     L.grmhd_prim2cons.argtypes = [vp, vp, vp, i32]
     L.grmhd_diag.argtypes = [vp, dp, dp]
+    L.grmhd_diag_full.argtypes = [vp, ctypes.POINTER(Horizon), vp]
     L.grmhd_get_prims.argtypes = [vp, vp, i32]
     L.grmhd_get_time.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.grmhd_get_codes.argtypes = [vp, vp]
@@ -242,6 +249,14 @@ class Context:
         _check(load().grmhd_diag(self._h, ctypes.byref(m), ctypes.byref(f)))
         return m.value, f.value
 
+    def diag_full(self):
+        """Horizon diagnostics (dict) and the radial profiles [6][n1]: Mdot, phi_B, Ldot, Edot,
+        ldot_in, ldot_out per radial cell."""
+        hz = Horizon()
+        rad = np.empty((6, self.grid.n1))
+        _check(load().grmhd_diag_full(self._h, ctypes.byref(hz), _ptr(rad)))
+        return ({k: getattr(hz, k) for k in ("mdot", "phi_b", "ldot", "edot", "phi_b_norm", "i_h")}, rad)
+
     def autotune(self, steps_per_candidate: int = 2) -> str:
         buf = ctypes.create_string_buffer(4096)
         _check(load().grmhd_autotune(self._h, int(steps_per_candidate), buf, len(buf)))
@@ -298,6 +313,14 @@ class Batch:
 
     def advance(self, steps: int):
         _check(load().grmhd_batch_advance(self._h, int(steps)))
+
+    def diag_full(self):
+        """Horizon diagnostics (dict) and the radial profiles [6][n1]: Mdot, phi_B, Ldot, Edot,
+        ldot_in, ldot_out per radial cell."""
+        hz = Horizon()
+        rad = np.empty((6, self.grid.n1))
+        _check(load().grmhd_diag_full(self._h, ctypes.byref(hz), _ptr(rad)))
+        return ({k: getattr(hz, k) for k in ("mdot", "phi_b", "ldot", "edot", "phi_b_norm", "i_h")}, rad)
 
     def autotune(self, steps_per_candidate: int = 2) -> str:
         buf = ctypes.create_string_buffer(4096)

@@ -45,3 +45,31 @@ def test_host_only_calls_work_without_a_gpu():
     fp = grmhd.footprint_bytes(torus_256cubed())
     # two 8-variable state arrays and three 9-variable flux arrays dominate: ~6 GB at 256^3
     assert 5.5e9 < fp < 7.5e9
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """sizeof and field offsets of the header's structs, compiled by the C compiler, equal the
+    ctypes mirrors the binding passes across the boundary."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    from paper_2205_02484_amd import grmhd
+    structs = {"grmhd_grid": grmhd.Grid, "grmhd_params": grmhd.Params, "grmhd_horizon": grmhd.Horizon}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "grmhd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

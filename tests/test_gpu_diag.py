@@ -1,0 +1,89 @@
+"""Parity of the device accretion diagnostics (grmhd_diag_full: Sec. 4.2) with the oracle's on the
+same state: the state the GPU reached after some steps is read back and given to the oracle, so
+only the diagnostic sums are compared.  The sums are signed and cancel strongly where inflow and
+outflow meet in a shell; the device adds in a fixed tree order and the oracle sequentially, so
+each shell sum is compared to 1e-12 of the sum of the magnitudes of its terms (at most 4096 terms
+per shell here: the worst-case difference of two summation orders is 4096 eps, about 5e-13, of
+that), and the ratios by the same bound carried through the quotient.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2205_02484_amd.torus_init import TorusConfig, make_torus
+from paper_2205_02484_amd.workloads import torus_2d_64, torus_128x64x64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02484_amd import grmhd
+    grmhd.load()
+    return grmhd
+
+
+def _check(G, c, nsteps, field3=0.0):
+    P0 = make_torus(c)
+    if field3:
+        P0[7] = field3 * P0[5]
+    ctx = G.Context(c, P0)
+    ctx.steps(nsteps)
+    P = ctx.get_prims()
+    hz, rad = ctx.diag_full()
+    m, f = ctx.diag()
+    ctx.close()
+    cfg = orc.make_cfg(c)
+    hzo, rado, iho, ab = orc.diag_full(cfg, P, with_absum=True)
+    assert hz["i_h"] == iho
+    assert hz["mdot"] == pytest.approx(m, rel=1e-13) and hz["phi_b"] == pytest.approx(f, rel=1e-13)
+    for q in range(4):
+        assert np.all(np.abs(rad[q] - rado[q]) <= 1e-12 * ab[q]), q
+    ok = rado[0] != 0.0
+    for q in (4, 5):
+        assert np.array_equal(np.isfinite(rad[q]), ok)
+        # rounding of the numerator and of the mass-flux denominator, each bounded by its magnitudes
+        tol = 1e-12 * (ab[q][ok] + np.abs(rado[q][ok]) * ab[0][ok]) / np.abs(rado[0][ok])
+        assert np.all(np.abs(rad[q][ok] - rado[q][ok]) <= tol), q
+    ih = iho
+    for k, q in (("mdot", 0), ("phi_b", 1), ("ldot", 2), ("edot", 3)):
+        assert abs(hz[k] - hzo[q]) <= 1e-12 * ab[q, ih], k
+    assert hz["phi_b_norm"] == pytest.approx(hz["phi_b"] / math.sqrt(abs(hz["mdot"])), rel=1e-15)
+    assert abs(hz["ldot"]) > 0.0 and hz["mdot"] < 0.0
+
+
+def test_diagnostics_2d_torus_after_ten_steps(G):
+    _check(G, torus_2d_64(), 10)
+
+
+def test_diagnostics_3d_torus_with_toroidal_field(G):
+    c = TorusConfig(n1=40, n2=24, n3=16, r_out=60.0, gam=13.0 / 9.0, delta=0.04, seed=11, cfl=0.45)
+    _check(G, c, 5, field3=0.3)
+
+
+def test_diagnostics_128x64x64_torus(G):
+    _check(G, torus_128x64x64(), 3)
+
+
+def test_diagnostics_reject_flat_grids(G):
+    class C:
+        pass
+    c = C()
+    c.coords = "cart"
+    c.n1, c.n2, c.n3 = 8, 8, 8
+    c.gam = 4.0 / 3.0
+    c.cfl = 0.4
+    c.xmin, c.xmax = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    P = np.zeros((8, 8, 8, 8))
+    P[0] = 1.0
+    P[1] = 1.0
+    ctx = G.Context(c, P)
+    with pytest.raises(G.GrmhdError) as ei:
+        ctx.diag_full()
+    assert ei.value.code == G.EINVAL
+    ctx.close()
