@@ -74,6 +74,8 @@ typedef struct {
     double bsq_rho_max, bsq_u_max, gamma_max, beta_entropy;
     double c2p_tol;
     int32_t c2p_maxit, fixup_max_rounds;
+    double r_br;                    /* > 0: radius where r(X1) turns hyper-exponential (Sec. 4.1) */
+    int32_t n_x, pad1;              /* power of the hyper-exponential term */
 } orc_cfg;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -87,12 +89,44 @@ typedef struct {
     double r;               /* KS radius (floors) */
 } Geom;
 
+/* Radial map of Sec. 4.1 (R_0 = 0): r = exp(X1) below x_b = ln r_br and
+ * r = exp(X1 + (X1 - x_b)^n_x) from there on (c->r_br <= 0: exp(X1) everywhere).  Complex so that
+ * the metric derivative can be taken by complex step; the branch follows the real part. */
+static double complex r_of_x1_c(const orc_cfg* c, double complex X1) {
+    if (c->r_br <= 0.0 || creal(X1) < log(c->r_br)) return cexp(X1);
+    double complex u = X1 - log(c->r_br), p = 1.0;
+    for (int k = 0; k < c->n_x; k++) p *= u;
+    return cexp(X1 + p);
+}
+/* dr/dX1 of that map */
+static double complex drdx1_c(const orc_cfg* c, double complex X1) {
+    double complex r = r_of_x1_c(c, X1);
+    if (c->r_br <= 0.0 || creal(X1) < log(c->r_br)) return r;
+    double complex u = X1 - log(c->r_br), p = 1.0;
+    for (int k = 0; k < c->n_x - 1; k++) p *= u;
+    return r * (1.0 + c->n_x * p);
+}
+
+/* Outer X1 of the grid: r(X1_out) = r_out, by bisection on [ln r_br, ln r_out] when the map is
+ * hyper-exponential there (r(X1) is increasing, and r(ln r_out) >= r_out). */
+static double x1_out(const orc_cfg* c) {
+    double hi = log(c->r_out);
+    if (c->r_br <= 0.0 || c->r_out <= c->r_br) return hi;
+    double lo = log(c->r_br);
+    for (int it = 0; it < 200; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (creal(r_of_x1_c(c, mid)) < c->r_out) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* Complex-valued MKS Kerr-Schild covariant metric, so that d/dX can be taken by complex step. */
-static void mks_gcov_c(double a, double hpar, double complex X1, double complex X2,
+static void mks_gcov_c(const orc_cfg* cf, double a, double hpar, double complex X1, double complex X2,
                        double complex g[4][4]) {
-    double complex r = cexp(X1);
+    double complex r = r_of_x1_c(cf, X1);
     double complex th = M_PI * X2 + 0.5 * (1.0 - hpar) * csin(2.0 * M_PI * X2);
-    double complex drdx = r;
+    double complex drdx = drdx1_c(cf, X1);
     double complex dthdx = M_PI * (1.0 + (1.0 - hpar) * ccos(2.0 * M_PI * X2));
     double complex cth = ccos(th), sth = csin(th);
     double complex s2 = sth * sth;
@@ -117,7 +151,7 @@ static void mks_gcov_c(double a, double hpar, double complex X1, double complex 
 static void grid_dx(const orc_cfg* c, double dx[4]) {
     dx[0] = 0.0;
     if (c->coords == ORC_MKS) {
-        dx[1] = (log(c->r_out) - log(c->r_in)) / c->n1;
+        dx[1] = (x1_out(c) - log(c->r_in)) / c->n1;
         dx[2] = 1.0 / c->n2;
         dx[3] = 2.0 * M_PI / c->n3;
     } else {
@@ -153,11 +187,12 @@ static void geom_point(const orc_cfg* c, double X1, double X2, int with_conn, Ge
     }
     const double a = c->a, hp = c->h;
     double complex gc[4][4];
-    mks_gcov_c(a, hp, X1, X2, gc);
+    mks_gcov_c(c, a, hp, X1, X2, gc);
     for (int m = 0; m < 4; m++)
         for (int n = 0; n < 4; n++) G->gcov[m][n] = creal(gc[m][n]);
     /* closed-form Kerr-Schild inverse, carried to MKS by the inverse Jacobian */
-    double r = exp(X1);
+    double r = creal(r_of_x1_c(c, X1));
+    double drdx = creal(drdx1_c(c, X1));
     double th = M_PI * X2 + 0.5 * (1.0 - hp) * sin(2.0 * M_PI * X2);
     double dthdx = M_PI * (1.0 + (1.0 - hp) * cos(2.0 * M_PI * X2));
     double cth = cos(th), sth = sin(th);
@@ -170,10 +205,10 @@ static void geom_point(const orc_cfg* c, double X1, double X2, int with_conn, Ge
     ksi[1][3] = ksi[3][1] = a / sig;
     ksi[2][2] = 1.0 / sig;
     ksi[3][3] = 1.0 / (sig * sth * sth);
-    double J[4] = {1.0, r, dthdx, 1.0};
+    double J[4] = {1.0, drdx, dthdx, 1.0};
     for (int m = 0; m < 4; m++)
         for (int n = 0; n < 4; n++) G->gcon[m][n] = ksi[m][n] / (J[m] * J[n]);
-    G->gdet = sig * fabs(sth) * r * dthdx;
+    G->gdet = sig * fabs(sth) * drdx * dthdx;
     G->alpha = 1.0 / sqrt(-G->gcon[0][0]);
     G->r = r;
     if (!with_conn) return;
@@ -181,10 +216,10 @@ static void geom_point(const orc_cfg* c, double X1, double X2, int with_conn, Ge
     const double hstep = 1e-30;
     double dg[4][4][4] = {{{0}}};
     double complex gp[4][4];
-    mks_gcov_c(a, hp, X1 + I * hstep, X2, gp);
+    mks_gcov_c(c, a, hp, X1 + I * hstep, X2, gp);
     for (int m = 0; m < 4; m++)
         for (int n = 0; n < 4; n++) dg[1][m][n] = cimag(gp[m][n]) / hstep;
-    mks_gcov_c(a, hp, X1, X2 + I * hstep, gp);
+    mks_gcov_c(c, a, hp, X1, X2 + I * hstep, gp);
     for (int m = 0; m < 4; m++)
         for (int n = 0; n < 4; n++) dg[2][m][n] = cimag(gp[m][n]) / hstep;
     /* Gamma_{s mu nu} = 1/2 (d_mu g_{s nu} + d_nu g_{s mu} - d_s g_{mu nu}) ; raise with g^{ls} */
@@ -1284,6 +1319,16 @@ int orc_diag_full(const orc_cfg* c, const double* Pint, double* hz, double* rad,
 }
 
 /* ---- single-point helpers for the pin tests ---- */
+
+/* Lower X1 face and X1 cell width of the grid (MKS). */
+int orc_grid_x1(const orc_cfg* c, double* x1lo, double* dx1) {
+    double dx[4];
+    grid_dx(c, dx);
+    *x1lo = log(c->r_in);
+    *dx1 = dx[1];
+    return 0;
+}
+
 
 int orc_geom(const orc_cfg* c, double X1, double X2, double* gcov, double* gcon, double* gdet,
              double* conn) {

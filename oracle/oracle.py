@@ -34,6 +34,7 @@ class OrcCfg(ctypes.Structure):
         ("gamma_max", ctypes.c_double), ("beta_entropy", ctypes.c_double),
         ("c2p_tol", ctypes.c_double),
         ("c2p_maxit", ctypes.c_int32), ("fixup_max_rounds", ctypes.c_int32),
+        ("r_br", ctypes.c_double), ("n_x", ctypes.c_int32), ("pad1", ctypes.c_int32),
     ]
 
 
@@ -64,6 +65,7 @@ def lib():
         L.orc_cons2prim.argtypes = [cp, dp, dp, bp]
         L.orc_diag.argtypes = [cp, dp, dp, dp]
         L.orc_diag_full.argtypes = [cp, dp, dp, dp, dp]
+        L.orc_grid_x1.argtypes = [cp, dp, dp]
         L.orc_geom.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.orc_point_state.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp] + [dp] * 10
         L.orc_point_c2p.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
@@ -117,6 +119,8 @@ def make_cfg(obj=None, **over) -> OrcCfg:
     c.c2p_tol = float(get("c2p_tol", 1e-10))
     c.c2p_maxit = int(get("c2p_maxit", 50))
     c.fixup_max_rounds = int(get("fixup_max_rounds", 8))
+    c.r_br = float(get("r_br", 0.0) or 0.0)
+    c.n_x = int(get("n_x", 4))
     return c
 
 
@@ -200,6 +204,13 @@ def diag_full(cfg: OrcCfg, P, with_absum: bool = False):
     if with_absum:
         return hz, rad, ih, ab
     return hz, rad, ih
+
+
+def grid_x1(cfg: OrcCfg):
+    """(lower X1 face, X1 cell width) of the grid."""
+    lo, dx = ctypes.c_double(), ctypes.c_double()
+    lib().orc_grid_x1(ctypes.byref(cfg), ctypes.byref(lo), ctypes.byref(dx))
+    return lo.value, dx.value
 
 
 def geom(cfg: OrcCfg, X1: float, X2: float):

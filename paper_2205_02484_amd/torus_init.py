@@ -10,7 +10,8 @@ Paper passages followed (arXiv 2205.02484):
     density normalised to rho_max = 1, pressure rescaled with it   -- Sec. "Physical models"
   * seed field A_phi = max(rho/rho_max - 0.2, 0), normalised by beta_0 -- same section, Eq. for A_phi
   * random perturbation of the gas pressure (4 per cent)              -- same section
-  * MKS grid r = exp(X1), theta(X2) refined towards the equator       -- Sec. "Metric, numerical grid"
+  * MKS grid r = exp(X1) (hyper-exponential beyond r_br), theta(X2) refined towards the equator
+                                                                      -- Sec. "Metric, numerical grid"
   * density/energy floors                                             -- Sec. "Flooring model"
 
 The FM torus is built from the constant angular momentum l = u^t u_phi.  With the ZAMO
@@ -56,6 +57,8 @@ class TorusConfig:
     cfl: float = 0.45
     kappa: float = 1e-3            # polytropic constant (cancels after normalisation)
     field: bool = True
+    r_br: float = 0.0              # > 0: radius where r(X1) turns hyper-exponential
+    n_x: int = 4                   # power of the hyper-exponential term
 
     @property
     def r_horizon(self) -> float:
@@ -74,14 +77,44 @@ class TorusConfig:
 # grid (MKS) -- the generator's own copy of the coordinate map
 # ----------------------------------------------------------------------------------------------
 
+def r_of_x1(cfg: TorusConfig, X1):
+    """(r, dr/dX1): r = exp(X1) below x_b = ln r_br, exp(X1 + (X1 - x_b)^n_x) beyond."""
+    X1 = np.asarray(X1, dtype=np.float64)
+    if cfg.r_br <= 0.0:
+        r = np.exp(X1)
+        return r, r
+    xb = math.log(cfg.r_br)
+    u = np.maximum(X1 - xb, 0.0)
+    r = np.exp(X1 + u ** cfg.n_x)
+    return r, r * (1.0 + cfg.n_x * u ** (cfg.n_x - 1))
+
+
+def x1_range(cfg: TorusConfig):
+    """(X1 at r_grid_in, X1 at r_out); the latter by bisection when the map is hyper-exponential."""
+    lo_x = math.log(cfg.r_grid_in)
+    hi = math.log(cfg.r_out)
+    if cfg.r_br <= 0.0 or cfg.r_out <= cfg.r_br:
+        return lo_x, hi
+    lo = math.log(cfg.r_br)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if float(r_of_x1(cfg, mid)[0]) < cfg.r_out:
+            lo = mid
+        else:
+            hi = mid
+    return lo_x, 0.5 * (lo + hi)
+
+
 def mks_centres(cfg: TorusConfig, i: np.ndarray, j: np.ndarray):
     """(r, theta, dtheta/dX2) at possibly fractional cell indices (i, j); centre of cell 0 is 0."""
-    x1lo = math.log(cfg.r_grid_in)
-    dx1 = (math.log(cfg.r_out) - x1lo) / cfg.n1
+    x1lo, x1hi = x1_range(cfg)
+    dx1 = (x1hi - x1lo) / cfg.n1
     dx2 = 1.0 / cfg.n2
     X1 = x1lo + (np.asarray(i, dtype=np.float64) + 0.5) * dx1
     X2 = (np.asarray(j, dtype=np.float64) + 0.5) * dx2
-    r = np.exp(X1)
+    r = r_of_x1(cfg, X1)[0]
     th = np.pi * X2 + 0.5 * (1.0 - cfg.h) * np.sin(2.0 * np.pi * X2)
     dth = np.pi * (1.0 + (1.0 - cfg.h) * np.cos(2.0 * np.pi * X2))
     return r, th, dth
@@ -148,15 +181,23 @@ def fm_torus_2d(cfg: TorusConfig, i: np.ndarray, j: np.ndarray):
     return rho, u, ut, uphi, inside
 
 
-def _mks_metric_cov(cfg: TorusConfig, r, th, dth):
-    """Non-zero MKS covariant components (tt, t1, t3, 11, 13, 22, 33) and sqrt(-g)."""
+def mks_drdx(cfg: TorusConfig, i: np.ndarray):
+    """dr/dX1 at (possibly fractional) radial cell indices i."""
+    x1lo, x1hi = x1_range(cfg)
+    return r_of_x1(cfg, x1lo + (np.asarray(i, dtype=np.float64) + 0.5) * (x1hi - x1lo) / cfg.n1)[1]
+
+
+def _mks_metric_cov(cfg: TorusConfig, r, th, dth, dr=None):
+    """Non-zero MKS covariant components (tt, t1, t3, 11, 13, 22, 33) and sqrt(-g); dr = dr/dX1
+    (default r, the plain exponential map)."""
     a = cfg.spin
     c = np.cos(th)
     s = np.sin(th)
     s2 = s * s
     sig = r * r + a * a * c * c
     z = 2.0 * r / sig
-    dr = r  # dr/dX1 for r = exp(X1)
+    if dr is None:
+        dr = r
     g = {
         "tt": -(1.0 - z),
         "t1": z * dr,
@@ -170,12 +211,15 @@ def _mks_metric_cov(cfg: TorusConfig, r, th, dth):
     return g, gdet, sig
 
 
-def _bsq(cfg, r, th, dth, ut1, ut3, B1, B2):
+def _bsq(cfg, r, th, dth, ut1, ut3, B1, B2, dr=None):
     """b^2 for u~ = (u~1, 0, u~3) and B = (B1, B2, 0) (generator-side helper)."""
-    g, _, sig = _mks_metric_cov(cfg, r, th, dth)
-    # lapse and shift from the KS inverse metric carried to MKS: g^{tt}=-(1+2r/Sigma), g^{t1}=2/Sigma
+    if dr is None:
+        dr = r
+    g, _, sig = _mks_metric_cov(cfg, r, th, dth, dr)
+    # lapse and shift from the KS inverse metric carried to MKS: g^{tt}=-(1+2r/Sigma),
+    # g^{t1} = (2r/Sigma)/(dr/dX1)
     gcon_tt = -(1.0 + 2.0 * r / sig)
-    gcon_t1 = 2.0 / sig
+    gcon_t1 = 2.0 / sig if cfg.r_br <= 0.0 else (2.0 * r / sig) / dr
     alpha = 1.0 / np.sqrt(-gcon_tt)
     lor = np.sqrt(1.0 + g["11"] * ut1 * ut1 + 2.0 * g["13"] * ut1 * ut3 + g["33"] * ut3 * ut3)
     ut = lor / alpha
@@ -204,13 +248,14 @@ def make_torus(cfg: TorusConfig) -> np.ndarray:
     u = u / rho_max
 
     r, th, dth = mks_centres(cfg, ii, jj)
-    g, gdet, sig = _mks_metric_cov(cfg, r, th, dth)
+    dr = mks_drdx(cfg, ii)
+    g, gdet, sig = _mks_metric_cov(cfg, r, th, dth, dr)
     # MKS contravariant velocity (u^r = u^theta = 0 in the torus, u^phi unchanged by BL->KS)
     u1 = np.zeros_like(ut)
     u3 = uphi
     # u~^i = u^i - u^t g^{ti}/g^{tt}; with KS g^{tt} = -(1+2r/Sigma), g^{t1}_MKS = (2r/Sigma)/r
     gcon_tt = -(1.0 + 2.0 * r / sig)
-    gcon_t1 = (2.0 * r / sig) / r
+    gcon_t1 = (2.0 * r / sig) / (r if cfg.r_br <= 0.0 else dr)
     ut1 = np.where(inside, u1 - ut * gcon_t1 / gcon_tt, 0.0)
     ut3 = np.where(inside, u3, 0.0)
 
@@ -222,7 +267,8 @@ def make_torus(cfg: TorusConfig) -> np.ndarray:
         rho_e = fm_torus_2d(cfg, ie, je)[0] / rho_max
         rc = 0.25 * (rho_e[:-1, :-1] + rho_e[1:, :-1] + rho_e[:-1, 1:] + rho_e[1:, 1:])
         aphi = np.maximum(rc - 0.2, 0.0)      # shape (n1+1, n2+1), corner (i,j) = lower-left of cell (i,j)
-        dx1 = (math.log(cfg.r_out) - math.log(cfg.r_grid_in)) / n1
+        x1lo, x1hi = x1_range(cfg)
+        dx1 = (x1hi - x1lo) / n1
         dx2 = 1.0 / n2
         B1 = (aphi[:-1, 1:] + aphi[1:, 1:] - aphi[:-1, :-1] - aphi[1:, :-1]) / (2.0 * dx2 * gdet)
         B2 = -(aphi[1:, :-1] + aphi[1:, 1:] - aphi[:-1, :-1] - aphi[:-1, 1:]) / (2.0 * dx1 * gdet)
@@ -238,7 +284,7 @@ def make_torus(cfg: TorusConfig) -> np.ndarray:
 
     if cfg.field:
         gam = cfg.gam
-        bsq = _bsq(cfg, r, th, dth, ut1, ut3, B1, B2)
+        bsq = _bsq(cfg, r, th, dth, ut1, ut3, B1, B2, dr)
         pb = 0.5 * bsq
         pg = (gam - 1.0) * u3d
         pb3 = np.broadcast_to(pb[:, :, None], shape)

@@ -97,3 +97,28 @@ def test_perturbation_is_seeded_and_bounded():
     ratio = a[1][inside] / p0[1][inside]
     assert ratio.min() >= 0.96 - 1e-12 and ratio.max() <= 1.04 + 1e-12
     assert ratio.std() > 0.01
+
+
+def test_torus_on_the_hyperexponential_grid():
+    """The paper's production grid (r_br = 400, n_X = 4, r_out = 5000, Sec. 4.1): the map reaches
+    r_out, is exp(X1) inside the break; corner-divergence-free field, beta normalised."""
+    c = TorusConfig(n1=96, n2=64, n3=1, r_out=5000.0, r_br=400.0, n_x=4, beta=100.0, delta=0.0)
+    P = make_torus(c)[..., 0]
+    ii, jj = np.meshgrid(np.arange(96), np.arange(64), indexing="ij")
+    r, th, dth = ti.mks_centres(c, ii, jj)
+    dr = ti.mks_drdx(c, ii)
+    x1lo, x1hi = ti.x1_range(c)
+    assert ti.r_of_x1(c, x1hi)[0] == pytest.approx(5000.0, rel=1e-12)
+    assert np.all(np.diff(r[:, 0]) > 0) and r[-1, 0] < 5000.0
+    # inside the break the map is exp(X1): dr/dX1 = r there, larger beyond
+    inner = r[:, 0] < 400.0
+    assert np.allclose(dr[inner], r[inner], rtol=1e-15) and np.all(dr[~inner] > r[~inner])
+    _, gdet, _ = ti._mks_metric_cov(c, r, th, dth, dr)
+    dx1 = (x1hi - x1lo) / 96
+    g1, g2 = gdet * P[5], gdet * P[6]
+    div = ((g1[1:, 1:] + g1[1:, :-1] - g1[:-1, 1:] - g1[:-1, :-1]) / (2 * dx1)
+           + (g2[1:, 1:] + g2[:-1, 1:] - g2[1:, :-1] - g2[:-1, :-1]) / (2 / 64))
+    assert np.abs(div).max() < 1e-14 * np.abs(g1).max() / dx1
+    bsq = ti._bsq(c, r, th, dth, P[2], P[4], P[5], P[6], dr)
+    inside = ti.fm_torus_2d(c, ii, jj)[4]
+    assert ((c.gam - 1) * P[1])[inside].max() / (0.5 * bsq).max() == pytest.approx(100.0, rel=1e-10)
