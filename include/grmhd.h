@@ -56,6 +56,12 @@ typedef struct {
     int32_t coords;
     double r_in, r_out, h;
     double xmin[3], xmax[3];
+    /* MKS radial map (Sec. 4.1, R_0 = 0): r = exp(X1) for X1 < ln r_br and
+     * r = exp(X1 + (X1 - ln r_br)^n_x) beyond; r_br <= 0 keeps exp(X1) on the whole grid
+     * (EINVAL unless r_br > r_in and 2 <= n_x <= 16 when r_br > 0).  X1 spans [ln r_in, X1_out]
+     * with r(X1_out) = r_out in n1 equal cells. */
+    double r_br;
+    int32_t n_x, reserved_;
 } grmhd_grid;
 
 /* Physics and numerics.  Defaults (grmhd_params_default) are the paper's values: cfl 0.45

@@ -85,6 +85,29 @@ Layout make_layout(const grmhd_grid& g) {
     return L;
 }
 
+// MKS radial map on the host: r(X1) = exp(X1) below ln r_br, exp(X1 + (X1 - ln r_br)^n_x) beyond.
+double host_r_of_x1(const grmhd_grid* g, double X1) {
+    if (!(g->r_br > 0.0) || X1 < std::log(g->r_br)) return std::exp(X1);
+    const double u = X1 - std::log(g->r_br);
+    double p = 1.0;
+    for (int k = 0; k < g->n_x; ++k) p *= u;
+    return std::exp(X1 + p);
+}
+
+// X1 of the outer grid edge, r(X1) = r_out: bisection on [ln r_br, ln r_out] (r increases with X1
+// and r(ln r_out) >= r_out) when the map is hyper-exponential there.
+double host_x1_out(const grmhd_grid* g) {
+    double hi = std::log(g->r_out);
+    if (!(g->r_br > 0.0) || g->r_out <= g->r_br) return hi;
+    double lo = std::log(g->r_br);
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (host_r_of_x1(g, mid) < g->r_out) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 // Multiplier and shift of FastDiv for a divisor 1 <= d < 2^31 (see grmhd_dev.h).
 FastDiv make_fastdiv(int32_t d) {
     uint32_t l = 0;
@@ -108,6 +131,8 @@ int validate(const grmhd_grid* g, const grmhd_params* p) {
         if (!(g->r_in > 0.0) || !(g->r_out > g->r_in)) return fail(GRMHD_EINVAL, "need 0 < r_in < r_out");
         if (!(g->h > 0.0) || !(g->h <= 2.0)) return fail(GRMHD_EINVAL, "MKS h must be in (0, 2]");
         if (!(std::fabs(p->spin) < 1.0)) return fail(GRMHD_EINVAL, "|spin| must be < 1");
+        if (g->r_br > 0.0 && (!(g->r_br > g->r_in) || g->n_x < 2 || g->n_x > 16))
+            return fail(GRMHD_EINVAL, "hyper-exponential map needs r_br > r_in and 2 <= n_x <= 16");
     } else {
         for (int d = 0; d < 3; ++d)
             if (!(g->xmax[d] > g->xmin[d])) return fail(GRMHD_EINVAL, "need xmin < xmax");
@@ -206,7 +231,7 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.dx[0] = 0.0;
     if (R.mks) {
         x1lo = std::log(g->r_in);
-        R.dx[1] = (std::log(g->r_out) - x1lo) / g->n1;
+        R.dx[1] = (host_x1_out(g) - x1lo) / g->n1;
         R.dx[2] = 1.0 / g->n2;
         R.dx[3] = 2.0 * M_PI / g->n3;
     } else {
@@ -252,6 +277,8 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     GeoArgs A{};
     A.n1 = g->n1; A.n2 = g->n2; A.mks = R.mks;
     A.x1lo = x1lo; A.dx1 = R.dx[1]; A.dx2 = R.dx[2];
+    A.xb = g->r_br > 0.0 ? std::log(g->r_br) : INFINITY;
+    A.nx = g->n_x;
     A.spin = p->spin; A.h = g->h;
     A.rho_fl_coef = p->rho_fl_coef; A.rho_fl_pow = p->rho_fl_pow;
     A.u_fl_coef = p->u_fl_coef; A.u_fl_pow = p->u_fl_pow; A.fl_abs = p->fl_abs;
@@ -284,7 +311,7 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     if (R.mks) {
         const double rh = 1.0 + std::sqrt(1.0 - p->spin * p->spin);
         for (int i = 0; i < g->n1; ++i)
-            if (std::exp(x1lo + (i + 0.5) * R.dx[1]) >= rh) { r->ih = i; break; }
+            if (host_r_of_x1(g, x1lo + (i + 0.5) * R.dx[1]) >= rh) { r->ih = i; break; }
     }
     *out = r;
     return GRMHD_OK;

@@ -6,6 +6,8 @@ namespace grmhd {
 
 struct GeoArgs {
     int n1, n2, mks;
+    int nx;          // power of the hyper-exponential radial term
+    double xb;       // ln r_br: X1 where r(X1) turns hyper-exponential (+inf: never)
     double x1lo, dx1, dx2, spin, h;
     double rho_fl_coef, rho_fl_pow, u_fl_coef, u_fl_pow, fl_abs;
     double* gc;

@@ -40,9 +40,30 @@ struct MetricPoint {
     double g[7], gi[6], gdet, alpha, d1[7], d2[7], r;
 };
 
-__device__ void mks_point(double X1, double X2, double a, double hh, bool derivs, MetricPoint& m) {
+// r(X1) of the MKS radial map (Sec. 4.1) with its first two X1 derivatives: exp(X1) below xb,
+// exp(X1 + u^nx) with u = X1 - xb beyond
+__device__ void radial_map(double X1, double xb, int nx, double& r, double& dr, double& d2r) {
+    if (!(X1 >= xb)) {
+        r = exp(X1);
+        dr = r;
+        d2r = r;
+        return;
+    }
+    const double u = X1 - xb;
+    double un2 = 1.0;  // u^(nx-2)
+    for (int k = 0; k < nx - 2; ++k) un2 *= u;
+    const double un1 = un2 * u, un = un1 * u;
+    const double f1 = 1.0 + nx * un1, f2 = nx * (nx - 1) * un2;
+    r = exp(X1 + un);
+    dr = r * f1;
+    d2r = r * (f1 * f1 + f2);
+}
+
+__device__ void mks_point(double X1, double X2, double a, double hh, double xb, int nx, bool derivs,
+                          MetricPoint& m) {
     const double PI = 3.14159265358979323846;
-    const double r = exp(X1);
+    double r, dr, d2r;
+    radial_map(X1, xb, nx, r, dr, d2r);
     const double s2pi = sin(2.0 * PI * X2), c2pi = cos(2.0 * PI * X2);
     const double th = PI * X2 + 0.5 * (1.0 - hh) * s2pi;
     const double dth = PI * (1.0 + (1.0 - hh) * c2pi);
@@ -54,7 +75,6 @@ __device__ void mks_point(double X1, double X2, double a, double hh, bool derivs
     const double sig = r * r + a2 * c * c;
     const double del = r * r - 2.0 * r + a2;
     const double z = 2.0 * r / sig;
-    const double dr = r;
     // Kerr-Schild g_{mu nu}: tt, tr, tphi, rr, rphi, thth, phiphi
     const double K[7] = {-(1.0 - z), z, -a * z * s2, 1.0 + z, -a * (1.0 + z) * s2, sig,
                          s2 * (sig + a2 * (1.0 + z) * s2)};
@@ -79,8 +99,8 @@ __device__ void mks_point(double X1, double X2, double a, double hh, bool derivs
                           s2 * dsig_r + a2 * s2 * s2 * dz_r};
     const double Kt[7] = {dz_t, dz_t, -a * (dz_t * s2 + z * ds2), dz_t, -a * (dz_t * s2 + (1.0 + z) * ds2), dsig_t,
                           ds2 * sig + s2 * dsig_t + a2 * (dz_t * s2 * s2 + (1.0 + z) * 2.0 * s2 * ds2)};
-    // d_1 of the Jacobian factors (dr/dX1 = r): t1 -> r, 11 -> 2 r^2, 13 -> r
-    const double J1[7] = {0.0, dr, 0.0, 2.0 * dr * dr, dr, 0.0, 0.0};
+    // d_1 of the Jacobian factors dr/dX1, (dr/dX1)^2, dr/dX1
+    const double J1[7] = {0.0, d2r, 0.0, 2.0 * dr * d2r, d2r, 0.0, 0.0};
     const double J2[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 2.0 * dth * d2th, 0.0};
     for (int n = 0; n < 7; ++n) {
         m.d1[n] = Kr[n] * dr * J[n] + K[n] * J1[n];
@@ -100,7 +120,7 @@ __global__ void k_geometry(GeoArgs A) {
         const double fj = j + 0.5 - (pass == 2 ? 0.5 : 0.0);
         MetricPoint m;
         if (A.mks) {
-            mks_point(A.x1lo + fi * A.dx1, fj * A.dx2, A.spin, A.h, pass == 0, m);
+            mks_point(A.x1lo + fi * A.dx1, fj * A.dx2, A.spin, A.h, A.xb, A.nx, pass == 0, m);
         } else {
             for (int n = 0; n < 7; ++n) m.g[n] = m.d1[n] = m.d2[n] = 0.0;
             m.g[0] = -1.0; m.g[3] = 1.0; m.g[5] = 1.0; m.g[6] = 1.0;

@@ -33,7 +33,8 @@ SYMBOLS = [
 class Grid(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
                 ("coords", ctypes.c_int32), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
-                ("h", ctypes.c_double), ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3)]
+                ("h", ctypes.c_double), ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3),
+                ("r_br", ctypes.c_double), ("n_x", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class Horizon(ctypes.Structure):
@@ -131,6 +132,8 @@ def make_grid(cfg, **over) -> Grid:
     xmin, xmax = get("xmin", (0.0, 0.0, 0.0)), get("xmax", (1.0, 1.0, 1.0))
     for d in range(3):
         g.xmin[d], g.xmax[d] = float(xmin[d]), float(xmax[d])
+    g.r_br = float(get("r_br", 0.0) or 0.0)
+    g.n_x = int(get("n_x", 4))
     return g
 
 

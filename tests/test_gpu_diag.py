@@ -87,3 +87,9 @@ def test_diagnostics_reject_flat_grids(G):
         ctx.diag_full()
     assert ei.value.code == G.EINVAL
     ctx.close()
+
+
+def test_diagnostics_on_the_hyperexponential_grid(G):
+    c = TorusConfig(n1=96, n2=64, n3=1, r_out=5000.0, r_br=400.0, n_x=4, gam=13.0 / 9.0, delta=0.04,
+                    seed=17, cfl=0.45)
+    _check(G, c, 5)

@@ -156,3 +156,12 @@ def test_autotuned_launch_shapes_give_identical_results(G):
     assert np.array_equal(plain.get_prims(), tuned.get_prims())
     plain.close()
     tuned.close()
+
+
+def test_hyperexponential_map_arguments_are_checked(G):
+    c = _cfgs()[0]
+    P = make_torus(c)
+    for bad in ({"r_br": 0.5 * c.r_grid_in, "n_x": 4}, {"r_br": 400.0, "n_x": 1}, {"r_br": 400.0, "n_x": 17}):
+        with pytest.raises(G.GrmhdError) as ei:
+            G.Context(c, P, **bad)
+        assert ei.value.code == G.EINVAL

@@ -214,3 +214,39 @@ def test_one_step_256cubed_torus_in_bench_configuration(G):
     Po, dto, nfo, _ = orc.step(cfg, P, 1)
     assert t == pytest.approx(dto[0], rel=1e-13)
     assert_parity(Pg, Po, 1e-12)
+
+
+def _hyperexp(n=(96, 64, 1), **kw):
+    """The paper's production radial grid (Sec. 4.1): hyper-exponential beyond r = 400, n_X = 4,
+    outer edge 5000 M."""
+    base = dict(n1=n[0], n2=n[1], n3=n[2], r_out=5000.0, r_br=400.0, n_x=4, gam=13.0 / 9.0, delta=0.04,
+                seed=17, cfl=0.45)
+    base.update(kw)
+    return TorusConfig(**base)
+
+
+def test_hyperexponential_grid_fluxes_and_steps(G):
+    c = _hyperexp()
+    P = make_torus(c)
+    ctx = G.Context(c, P)
+    cfg = orc.make_cfg(c)
+    for d in (1, 2):
+        Fg, cg = ctx.debug_fluxes(d)
+        Fo, co = orc.fluxes(cfg, P, d)
+        assert scaled_abs_err(Fg, Fo) < 1e-12, d
+        assert cg == pytest.approx(co, rel=1e-13)
+    ctx.close()
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 1)
+    assert dtg[0] == pytest.approx(dto[0], rel=1e-13)
+    assert np.array_equal(cg, co)
+    assert_parity(Pg, Po, 1e-12)
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 10)
+    assert_parity(Pg, Po, 1e-8)
+
+
+def test_hyperexponential_grid_3d_step(G):
+    c = _hyperexp((48, 24, 16))
+    P = make_torus(c)
+    Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 1)
+    assert np.array_equal(cg, co)
+    assert_parity(Pg, Po, 1e-12)
