@@ -151,6 +151,16 @@ int grmhd_get_codes(grmhd_ctx* ctx, int8_t* codes);
  * those faces.  Diagnostic entry point for flux parity. */
 int grmhd_debug_fluxes(grmhd_ctx* ctx, int32_t d, double* F, double* cmax);
 
+/* Fixup rounds of Sec. 2.3 (averaging procedure) on a given state.  `pout` ([8][n1][n2][n3], host,
+ * in/out) is a stage output whose cells with code[] == -1 failed (their values are not read),
+ * `pin` the stage input; code[] (host, in/out, values -1..3) marks the failed cells.  The device
+ * fixup kernel runs its Jacobi rounds (at most params.fixup_max_rounds): on return pout holds the
+ * fixed state (floors applied to fixed cells; cells left unfixed carry their pin values), code[]
+ * is 3 for cells fixed by averaging and still -1 for cells left unfixed, *left (nullable) counts
+ * those.  The context's state becomes the returned pout.  Diagnostic entry point for fixup
+ * parity; EINVAL on NULL pointers, NaN in pin or codes outside -1..3. */
+int grmhd_debug_fixup(grmhd_ctx* ctx, double* pout, const double* pin, int8_t* code, int64_t* left);
+
 /* Measurement: with timing on, later steps run as plain launches with a HIP event pair recorded
  * on the context's stream around every kernel.  grmhd_kernel_times waits for them and returns
  * the average duration (ms) and launch count per kernel kind, in this order: 0 boundary ghosts,

@@ -831,6 +831,74 @@ int grmhd_get_codes(grmhd_ctx* c, int8_t* codes) {
     return GRMHD_OK;
 }
 
+int grmhd_debug_fixup(grmhd_ctx* c, double* pout, const double* pin, int8_t* code, int64_t* left) {
+    if (!c || !pout || !pin || !code) return fail(GRMHD_EINVAL, "NULL argument");
+    Run* r = c->run;
+    const RunDev& R = r->h;
+    Engine& E = c->eng;
+    if (E.runs.size() != 1) return fail(GRMHD_EINVAL, "context holds more than one run");
+    if (E.dirty) {
+        int rc = E.rebuild();
+        if (rc) return rc;
+    }
+    const int64_t n = (int64_t)R.n1 * R.n2 * R.n3;
+    if (!host_finite(pin, NPR * n)) return fail(GRMHD_EINVAL, "pin holds NaN/Inf");
+    // the run's code array (ghosted layout, ghosts 0) and the list of failed interior cells
+    std::vector<int8_t> full((size_t)R.vs, 0);
+    std::vector<int32_t> fails;
+    for (int i = 0; i < R.n1; ++i)
+        for (int j = 0; j < R.n2; ++j)
+            for (int k = 0; k < R.n3; ++k) {
+                const int64_t e = ((int64_t)i * R.n2 + j) * R.n3 + k;
+                const int8_t cd = code[e];
+                if (cd < -1 || cd > 3) return fail(GRMHD_EINVAL, "codes must be in [-1, 3]");
+                full[(size_t)((i + NG) * R.s1 + (j + NG) * R.s2 + k)] = cd;
+                if (cd == -1) fails.push_back((int32_t)e);
+            }
+    hipStream_t st = E.st;
+    double* d = nullptr;
+    int8_t* dc = nullptr;
+    HIPCHK(hipMalloc(&d, 2 * NPR * n * sizeof(double)));
+    if (hipMalloc(&dc, n) != hipSuccess) {
+        (void)hipFree(d);
+        return fail(GRMHD_ENOMEM, "debug_fixup: staging allocation failed");
+    }
+    const int32_t nf = (int32_t)fails.size();
+    hipError_t e = hipMemcpyAsync(d, pout, NPR * n * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d + NPR * n, pin, NPR * n * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        launch_load(R, d, 1, st);            // stage output -> P^{n+1/2}
+        launch_load(R, d + NPR * n, 0, st);  // stage input  -> P^n
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(R.code, full.data(), full.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && nf)
+        e = hipMemcpyAsync(R.fail_list, fails.data(), fails.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&R.var->fail_count, &nf, sizeof(nf), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        launch_fixup(E.d_runs, 1, 1, st);     // stage-1 roles: output P^{n+1/2}, input P^n
+        e = hipGetLastError();
+    }
+    // the fixed stage output becomes the context's state
+    if (e == hipSuccess) e = hipMemcpyAsync(R.P, R.Ph, (size_t)NPR * R.vs * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        launch_store(R, d, R.code, dc, st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(pout, d, NPR * n * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(code, dc, n, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d);
+    (void)hipFree(dc);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "debug_fixup: %s", hipGetErrorString(e));
+    if (left) {
+        int64_t m = 0;
+        for (int64_t x = 0; x < n; ++x) m += code[x] == -1;
+        *left = m;
+    }
+    return GRMHD_OK;
+}
+
 int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     if (!c || !F) return fail(GRMHD_EINVAL, "NULL argument");
     Run* r = c->run;

@@ -24,7 +24,7 @@ LLF, HLL = 0, 1
 SYMBOLS = [
     "grmhd_params_default", "grmhd_init", "grmhd_step", "grmhd_steps", "grmhd_cons2prim",
     "grmhd_prim2cons", "grmhd_diag", "grmhd_diag_full", "grmhd_get_prims", "grmhd_get_time", "grmhd_get_codes",
-    "grmhd_debug_fluxes", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
+    "grmhd_debug_fluxes", "grmhd_debug_fixup", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
     "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_autotune", "grmhd_batch_poll",
     "grmhd_batch_fetch", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
 ]
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_get_time.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.grmhd_get_codes.argtypes = [vp, vp]
     L.grmhd_debug_fluxes.argtypes = [vp, i32, vp, dp]
+    L.grmhd_debug_fixup.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
     L.grmhd_kernel_timing.argtypes = [vp, i32]
     L.grmhd_kernel_times.argtypes = [vp, dp, ctypes.POINTER(i64), i32]
     L.grmhd_autotune.argtypes = [vp, i32, ctypes.c_char_p, i32]
@@ -276,6 +277,16 @@ class Context:
         cnt = (ctypes.c_int64 * n)()
         _check(load().grmhd_kernel_times(self._h, ms, cnt, n))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KERNELS)}
+
+    def debug_fixup(self, pout, pin, code):
+        """Device fixup rounds on (pout, pin, code); returns (fixed P, codes, cells left)."""
+        shape = (8, self.grid.n1, self.grid.n2, self.grid.n3)
+        P = np.ascontiguousarray(pout, dtype=np.float64).reshape(shape).copy()
+        Pi = np.ascontiguousarray(pin, dtype=np.float64).reshape(shape)
+        cd = np.ascontiguousarray(code, dtype=np.int8).reshape(shape[1:]).copy()
+        left = ctypes.c_int64()
+        _check(load().grmhd_debug_fixup(self._h, _ptr(P), _ptr(Pi), cd.ctypes.data, ctypes.byref(left)))
+        return P, cd, left.value
 
     def debug_fluxes(self, d: int):
         m = [self.grid.n1, self.grid.n2, self.grid.n3]

@@ -1,0 +1,85 @@
+"""Parity of the device fixup rounds (Sec. 2.3, averaging procedure) with the oracle's, through
+grmhd_debug_fixup: the same stage output, stage input and failure mask go to both.  The mask
+holds an isolated cell (4-cross average), a diagonal-only cell, a 3 x 3 block (filled over Jacobi
+rounds), cells on the radial and polar edges of the interior (partial neighbour sets) and a block
+too large for the allowed rounds (its centre keeps the stage input).  The non-field primitives of
+the failed cells hold NaN in the stage output, so any read of them would show (their field comes
+from the conserved field and stays valid, as in a step).  Both sides add the same neighbour values in the
+same order and apply the same floors, so the results must agree to round-off.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2205_02484_amd.torus_init import TorusConfig, make_torus
+from paper_2205_02484_amd.workloads import torus_2d_64
+from tests._parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02484_amd import grmhd
+    grmhd.load()
+    return grmhd
+
+
+def _mask(n1, n2, n3):
+    code = np.zeros((n1, n2, n3), dtype=np.int8)
+    k = n3 // 2
+    code[10, 20, k] = -1                          # isolated: cross average
+    code[30, 30, k] = code[31, 30, k] = -1        # neighbours of each other: diagonal average
+    code[40:43, 10:13, :] = -1                    # 3 x 3 block in every phi slice
+    code[0, 5, 0] = -1                            # inner radial edge: partial neighbours
+    code[n1 - 1, n2 - 1, 0] = -1                  # corner of the interior
+    code[50:57, 40:47, k] = -1                    # 7 x 7 block: centre unreachable in 2 rounds
+    return code
+
+
+@pytest.mark.parametrize("which", ["2d", "3d"])
+@pytest.mark.parametrize("rounds", [2, 8])
+def test_device_fixups_match_the_oracle(G, which, rounds):
+    c = torus_2d_64() if which == "2d" else TorusConfig(n1=64, n2=48, n3=4, r_out=60.0, gam=13.0 / 9.0,
+                                                           delta=0.04, seed=11, cfl=0.45)
+    P = make_torus(c)
+    rng = np.random.default_rng(3)
+    Pin = P.copy()
+    Pin[0:2] *= 1.0 + 0.01 * rng.random(P.shape[1:])
+    code = _mask(c.n1, c.n2, c.n3)
+    Pout = P * (1.0 + 1e-3 * rng.standard_normal(P.shape))
+    Pout[0:2] = np.abs(Pout[0:2])
+    Pout[0:5, code == -1] = np.nan                  # B of a failed cell comes from U: it stays valid
+    ctx = G.Context(c, P, fixup_max_rounds=rounds)
+    Pg, cg, left_g = ctx.debug_fixup(Pout, Pin, code)
+    # the context's state is now the fixed stage output
+    assert np.array_equal(ctx.get_prims(), Pg)
+    ctx.close()
+    cfg = orc.make_cfg(c, fixup_max_rounds=rounds)
+    Po, co, left_o = orc.fixups(cfg, Pout.copy(), Pin, code.copy())
+    assert np.array_equal(cg, co)
+    assert left_g == left_o
+    assert (left_g > 0) == (rounds == 2)
+    assert np.isfinite(Pg).all()
+    assert_parity(Pg, Po, 1e-14)
+    # untouched cells are untouched, unfixed cells carry the stage input
+    ok = code >= 0
+    assert np.array_equal(Pg[:, ok], Pout[:, ok])
+    stuck = cg == -1
+    assert np.array_equal(Pg[:, stuck], Pin[:, stuck])
+    assert (cg[code == -1] != -1).sum() > 0 and np.all(cg[code == -1] != 0)
+
+
+def test_debug_fixup_rejects_bad_codes(G):
+    c = torus_2d_64()
+    P = make_torus(c)
+    ctx = G.Context(c, P)
+    code = np.zeros((c.n1, c.n2, c.n3), dtype=np.int8)
+    code[3, 3, 0] = 7
+    with pytest.raises(G.GrmhdError) as ei:
+        ctx.debug_fixup(P, P, code)
+    assert ei.value.code == G.EINVAL
+    ctx.close()
