@@ -59,3 +59,23 @@ def test_thousand_steps_128x64x64_stable_and_divergence_free(G):
     # the torus is still there: its density maximum moved little over a small fraction of an orbit
     assert 0.5 < P1[0].max() / P0[0].max() < 1.5
     assert math.isfinite(mdot) and math.isfinite(phib)
+
+
+def test_thousand_steps_2d_64_torus_keeps_corner_divergence(G):
+    """The 64^2 torus at CFL 0.8 for 1000 steps: corner div of sqrt(-g) B stays at round-off."""
+    from paper_2205_02484_amd.workloads import torus_2d_64
+    c = torus_2d_64()
+    P0 = make_torus(c)
+    cfg = orc.make_cfg(c)
+    gd = _centre_gdet(cfg)[..., None]
+    dx = [(math.log(cfg.r_out) - math.log(cfg.r_in)) / c.n1, 1.0 / c.n2]
+    bscale = np.abs(P0[5:7] * gd[None]).max() / min(dx)
+    ctx = G.Context(c, P0)
+    ctx.steps(1000)
+    t, nstep, nfail = ctx.get_time()
+    P1 = ctx.get_prims()
+    ctx.close()
+    d1 = corner_divb(P1, gd, dx, 2)
+    print(f"64^2 torus, 1000 steps to t = {t:.2f} M: max corner div / scale = {np.abs(d1).max() / bscale:.2e}")
+    assert nstep == 1000 and np.isfinite(P1).all()
+    assert np.abs(d1).max() < 1e-13 * bscale

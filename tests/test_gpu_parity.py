@@ -250,3 +250,30 @@ def test_hyperexponential_grid_3d_step(G):
     Pg, Po, dtg, dto, cg, co, _ = _run_both(G, c, P, 1)
     assert np.array_equal(cg, co)
     assert_parity(Pg, Po, 1e-12)
+
+
+def test_unphysical_conserved_states_fail_like_the_oracle(G):
+    """Fault injection through grmhd_cons2prim: negative D, zero D, negative entropy in a low-beta
+    cell (entropy method only), and momentum far above what the energy allows (the energy methods
+    fail, the entropy method takes over); the codes and every inverted cell agree with the oracle."""
+    c = _small3d()
+    P = make_torus(c)
+    cfg = orc.make_cfg(c)
+    U = orc.prim2cons(cfg, P)
+    ctx = G.Context(c, P)
+    bad = [(5, 5, 3), (20, 12, 7), (30, 18, 1), (12, 3, 9)]
+    U[0][bad[0]] = -abs(U[0][bad[0]])                 # D < 0
+    guess = P.copy()
+    guess[5:8][(slice(None),) + bad[1]] *= 1e3        # beta of the guess << 1e-2: entropy only
+    U[8][bad[1]] = -abs(U[8][bad[1]])                 # S < 0
+    U[2][bad[2]] *= 1e6                               # |Q| far above the energy: no v^2 < 1
+    U[0][bad[3]] = 0.0                                # D = 0
+    Pg, cg = ctx.cons2prim(U, guess)
+    Po, co = orc.cons2prim(cfg, U, guess)
+    ctx.close()
+    assert np.array_equal(cg, co)
+    for b in (bad[0], bad[1], bad[3]):
+        assert co[b] == -1, b
+    assert co[bad[2]] == 2          # the energy methods fail; the entropy method still inverts it
+    ok = co >= 0
+    assert_parity(np.where(ok[None], Pg, 0.0), np.where(ok[None], Po, 0.0), 1e-12)
