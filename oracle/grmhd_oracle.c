@@ -75,7 +75,8 @@ typedef struct {
     double c2p_tol;
     int32_t c2p_maxit, fixup_max_rounds;
     double r_br;                    /* > 0: radius where r(X1) turns hyper-exponential (Sec. 4.1) */
-    int32_t n_x, pad1;              /* power of the hyper-exponential term */
+    int32_t n_x;                    /* power of the hyper-exponential term */
+    int32_t recon;                  /* 0: PLM with the MC limiter (Sec. 2.2); 1: PPM (Colella-Woodward 1984) */
 } orc_cfg;
 
 /* ------------------------------------------------------------------------------------------ */
@@ -322,6 +323,49 @@ static void wave_speeds(const State* S, const Geom* G, int d, double gam, double
     double r2 = (-B - sq) / (2.0 * A);
     *c1 = r1 > r2 ? r1 : r2;
     *c2 = r1 > r2 ? r2 : r1;
+}
+
+double orc_mc_slope(double qm, double q0, double qp);
+
+/* PPM of Colella & Woodward (1984), the reconstruction Sec. 2.2 names as the upgrade of PLM.
+ * Interface value between cells j and j+1 from four cell values (their Eq. 1.6 with the limited
+ * slopes of Eqs. 1.7-1.8, which are the MC slopes below):
+ *   a_{j+1/2} = a_j + (a_{j+1} - a_j)/2 - (da_{j+1} - da_j)/6. */
+static double ppm_interface(double am1, double a0, double ap1, double ap2) {
+    double d0 = orc_mc_slope(am1, a0, ap1);
+    double d1 = orc_mc_slope(a0, ap1, ap2);
+    return a0 + 0.5 * (ap1 - a0) - (d1 - d0) / 6.0;
+}
+
+/* Edge values (aL, aR) of the parabola in a cell of average a0 with interface values aL, aR, after
+ * the monotonicity constraints of their Eq. 1.10: a local extremum gives the flat profile; an
+ * edge value that would put the parabola's extremum inside the cell is moved so that it sits on
+ * the opposite edge. */
+static void ppm_constrain(double a0, double* aL, double* aR) {
+    double l = *aL, r = *aR;
+    if ((r - a0) * (a0 - l) <= 0.0) {
+        l = a0;
+        r = a0;
+    } else {
+        double da = r - l, a6 = 6.0 * (a0 - 0.5 * (l + r));
+        if (da * a6 > da * da) l = 3.0 * a0 - 2.0 * r;
+        else if (-da * da > da * a6) r = 3.0 * a0 - 2.0 * l;
+    }
+    *aL = l;
+    *aR = r;
+}
+
+/* PPM states on the face between cells 2 and 3 of six consecutive cells q[0..5]: the left state is
+ * the upper edge of cell 2, the right state the lower edge of cell 3. */
+void orc_ppm_face(const double* q, double* ql, double* qr) {
+    double i12 = ppm_interface(q[0], q[1], q[2], q[3]);  /* between cells 1 and 2 */
+    double i23 = ppm_interface(q[1], q[2], q[3], q[4]);  /* between cells 2 and 3 (the face) */
+    double i34 = ppm_interface(q[2], q[3], q[4], q[5]);  /* between cells 3 and 4 */
+    double l2 = i12, r2 = i23, l3 = i23, r3 = i34;
+    ppm_constrain(q[2], &l2, &r2);
+    ppm_constrain(q[3], &l3, &r3);
+    *ql = r2;
+    *qr = l3;
 }
 
 /* MC limiter in the paper's case form; READING-1: the last case is the signed (q_{I+1}-q_{I-1})/2. */
@@ -614,10 +658,12 @@ static int grid_init(Grid* g, const orc_cfg* c) {
     memset(g, 0, sizeof(*g));
     g->c = c;
     g->n[1] = c->n1; g->n[2] = c->n2; g->n[3] = c->n3;
+    if (c->recon != 0 && c->recon != 1) return -1;
     for (int d = 1; d <= 3; d++) {
         if (g->n[d] < 1) return -1;
         g->active[d] = g->n[d] > 1;
-        g->g[d] = g->active[d] ? 2 : 0;
+        g->g[d] = g->active[d] ? (c->recon == 1 ? 3 : 2) : 0;  /* PPM faces reach 3 cells out */
+        if (g->active[d] && g->n[d] < g->g[d]) return -1;      /* ghosts copy from that many cells */
         g->N[d] = g->n[d] + 2 * g->g[d];
     }
     if (c->coords == ORC_MKS && (!g->active[1] || !g->active[2])) return -1;
@@ -762,11 +808,20 @@ static void compute_fluxes(const Grid* g, const double* P, int d, double* F, dou
                 const double* p0 = &P[cidx(g, i, j, k) * NPR];
                 const double* pp1 = &P[cidx(g, i + di, j + dj, k + dk) * NPR];
                 double Pl[NPR], Pr[NPR];
-                for (int v = 0; v < NPR; v++) {
-                    double dql = orc_mc_slope(pm2[v], pm1[v], p0[v]);
-                    double dqr = orc_mc_slope(pm1[v], p0[v], pp1[v]);
-                    Pl[v] = pm1[v] + 0.5 * dql;
-                    Pr[v] = p0[v] - 0.5 * dqr;
+                if (g->c->recon == 1) {
+                    const double* pm3 = &P[cidx(g, i - 3 * di, j - 3 * dj, k - 3 * dk) * NPR];
+                    const double* pp2 = &P[cidx(g, i + 2 * di, j + 2 * dj, k + 2 * dk) * NPR];
+                    for (int v = 0; v < NPR; v++) {
+                        double q6[6] = {pm3[v], pm2[v], pm1[v], p0[v], pp1[v], pp2[v]};
+                        orc_ppm_face(q6, &Pl[v], &Pr[v]);
+                    }
+                } else {
+                    for (int v = 0; v < NPR; v++) {
+                        double dql = orc_mc_slope(pm2[v], pm1[v], p0[v]);
+                        double dqr = orc_mc_slope(pm1[v], p0[v], pp1[v]);
+                        Pl[v] = pm1[v] + 0.5 * dql;
+                        Pr[v] = p0[v] - 0.5 * dqr;
+                    }
                 }
                 const Geom* G = d == 1 ? &g->gf1[gidx(g, i, j)]
                               : (d == 2 ? &g->gf2[gidx(g, i, j)] : &g->gc[gidx(g, i, j)]);

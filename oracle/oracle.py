@@ -34,7 +34,7 @@ class OrcCfg(ctypes.Structure):
         ("gamma_max", ctypes.c_double), ("beta_entropy", ctypes.c_double),
         ("c2p_tol", ctypes.c_double),
         ("c2p_maxit", ctypes.c_int32), ("fixup_max_rounds", ctypes.c_int32),
-        ("r_br", ctypes.c_double), ("n_x", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("r_br", ctypes.c_double), ("n_x", ctypes.c_int32), ("recon", ctypes.c_int32),
     ]
 
 
@@ -66,6 +66,7 @@ def lib():
         L.orc_diag.argtypes = [cp, dp, dp, dp]
         L.orc_diag_full.argtypes = [cp, dp, dp, dp, dp]
         L.orc_grid_x1.argtypes = [cp, dp, dp]
+        L.orc_ppm_face.argtypes = [dp, dp, dp]
         L.orc_geom.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         L.orc_point_state.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp] + [dp] * 10
         L.orc_point_c2p.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
@@ -121,6 +122,8 @@ def make_cfg(obj=None, **over) -> OrcCfg:
     c.fixup_max_rounds = int(get("fixup_max_rounds", 8))
     c.r_br = float(get("r_br", 0.0) or 0.0)
     c.n_x = int(get("n_x", 4))
+    rec = get("recon", "plm")
+    c.recon = 1 if rec in ("ppm", 1) else 0
     return c
 
 
@@ -204,6 +207,14 @@ def diag_full(cfg: OrcCfg, P, with_absum: bool = False):
     if with_absum:
         return hz, rad, ih, ab
     return hz, rad, ih
+
+
+def ppm_face(q6):
+    """PPM (left, right) states on the face between cells 2 and 3 of six cell values."""
+    q = np.ascontiguousarray(q6, dtype=np.float64)
+    l, r = ctypes.c_double(), ctypes.c_double()
+    lib().orc_ppm_face(_dp(q), ctypes.byref(l), ctypes.byref(r))
+    return l.value, r.value
 
 
 def grid_x1(cfg: OrcCfg):
