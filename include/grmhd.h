@@ -45,6 +45,10 @@ enum {
 
 enum { GRMHD_MKS = 0, GRMHD_MINKOWSKI_CART = 1 };
 enum { GRMHD_LLF = 0, GRMHD_HLL = 1 };
+/* Reconstruction of the face states (Sec. 2.2): piecewise linear with the MC limiter, or PPM
+ * (Colella & Woodward 1984, the upgrade Sec. 2.2 names), which needs >= 3 cells along every
+ * direction with more than one cell. */
+enum { GRMHD_PLM = 0, GRMHD_PPM = 1 };
 
 /* Grid.  GRMHD_MKS (Sec. 4.1): r = exp(X1) on [r_in, r_out], theta = pi X2 + (1-h)/2 sin(2 pi X2)
  * on X2 in [0,1], phi = X3 on [0, 2 pi); radial inflow/outflow, polar reflection, periodic phi.
@@ -70,7 +74,8 @@ typedef struct {
  * Newton-Raphson tolerance 1e-10 (Sec. 2.3). */
 typedef struct {
     double spin, gam, cfl;
-    int32_t riemann, reserved0;
+    int32_t riemann;   /* GRMHD_LLF or GRMHD_HLL */
+    int32_t recon;     /* GRMHD_PLM (default) or GRMHD_PPM */
     double rho_fl_coef, rho_fl_pow, u_fl_coef, u_fl_pow, fl_abs;
     double bsq_rho_max, bsq_u_max, gamma_max, beta_entropy;
     double c2p_tol;
@@ -87,7 +92,7 @@ void grmhd_params_default(grmhd_params* p);
  * supplies a floored state) and builds the metric, inverse-metric and source tables (Sec. 4.1
  * metric, Sec. 2.2 centred source) on the device.  `hip_stream` is a hipStream_t the context
  * launches on (NULL: the library creates a non-blocking stream of its own).  EINVAL on bad
- * sizes/NaN or when (n1+4)(n2+4)n3 >= 2^29 (each per-variable device array, ghosts included,
+ * sizes/NaN or when (n1+6)(n2+6)n3 >= 2^29 (each per-variable device array, ghosts included,
  * must stay below 4 GiB: kernels address it with 32-bit byte offsets; about 800^3 cells per run),
  * ENOMEM when the device state does not fit. */
 int grmhd_init(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_params* params,

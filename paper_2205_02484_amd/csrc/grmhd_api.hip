@@ -37,8 +37,16 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 // block tables: ghosts; fluxes per direction and update, each once over the runs with n3 % 64 == 0
-// (a wave's cells share (r, theta): scalar metric loads) and once over the other runs
-enum { KB_BOUND = 0, KB_F1, KB_F2, KB_F3, KB_F1N, KB_F2N, KB_F3N, KB_UPD, KB_UPDN, NK };
+// (a wave's cells share (r, theta): scalar metric loads) and once over the other runs; the flux
+// tables also split PLM runs (KB_F*) from PPM runs (KB_P*), which have kernels of their own
+enum {
+    KB_BOUND = 0,
+    KB_F1, KB_F2, KB_F3, KB_F1N, KB_F2N, KB_F3N,
+    KB_P1, KB_P2, KB_P3, KB_P1N, KB_P2N, KB_P3N,
+    KB_UPD, KB_UPDN, NK
+};
+// flux table of direction d for runs with (uni, ppm)
+constexpr int flux_kind(int d, bool uni, bool ppm) { return KB_F1 + (d - 1) + (uni ? 0 : 3) + (ppm ? 6 : 0); }
 
 // Launch shape of one stage-kernel kind: threads per workgroup and block order (bit 0 set:
 // XCD-contiguous).  The autotuner picks one per kind.
@@ -122,7 +130,7 @@ int validate(const grmhd_grid* g, const grmhd_params* p) {
     if (!g || !p) return fail(GRMHD_EINVAL, "grid and params are required");
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) return fail(GRMHD_EINVAL, "grid sizes must be >= 1");
     if ((int64_t)g->n1 * g->n2 * g->n3 >= (1ll << 31)) return fail(GRMHD_EINVAL, "grid too large (>= 2^31 cells)");
-    // every per-variable array is addressed with 32-bit byte offsets: (n1+4)(n2+4) n3 cells < 2^29
+    // every per-variable array is addressed with 32-bit byte offsets: (n1+6)(n2+6) n3 cells < 2^29
     if ((int64_t)(g->n1 + 2 * NG) * (g->n2 + 2 * NG) * g->n3 >= (1ll << 29))
         return fail(GRMHD_EINVAL, "grid too large for one run (more than 2^29 cells with ghosts)");
     if (g->coords != GRMHD_MKS && g->coords != GRMHD_MINKOWSKI_CART) return fail(GRMHD_EINVAL, "unknown coords");
@@ -140,6 +148,10 @@ int validate(const grmhd_grid* g, const grmhd_params* p) {
     if (!(p->gam > 1.0)) return fail(GRMHD_EINVAL, "gamma must be > 1");
     if (!(p->cfl > 0.0)) return fail(GRMHD_EINVAL, "cfl must be > 0");
     if (p->riemann != GRMHD_LLF && p->riemann != GRMHD_HLL) return fail(GRMHD_EINVAL, "unknown riemann solver");
+    if (p->recon != GRMHD_PLM && p->recon != GRMHD_PPM) return fail(GRMHD_EINVAL, "unknown reconstruction");
+    // PPM reads three cells out: periodic wraps and polar reflections need that many active cells
+    if (p->recon == GRMHD_PPM && ((g->n1 > 1 && g->n1 < 3) || (g->n2 > 1 && g->n2 < 3) || (g->n3 > 1 && g->n3 < 3)))
+        return fail(GRMHD_EINVAL, "PPM needs at least 3 cells along every direction with more than one");
     if (!(p->bsq_rho_max > 0.0) || !(p->bsq_u_max > 0.0) || !(p->gamma_max >= 1.0))
         return fail(GRMHD_EINVAL, "ceilings must be positive, gamma_max >= 1");
     if (!(p->c2p_tol > 0.0) || p->c2p_maxit < 0 || p->fixup_max_rounds < 0) return fail(GRMHD_EINVAL, "bad inversion controls");
@@ -222,6 +234,7 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.act1 = g->n1 > 1; R.act2 = g->n2 > 1; R.act3 = g->n3 > 1;
     R.mks = g->coords == GRMHD_MKS;
     R.riemann = p->riemann;
+    R.ppm = p->recon == GRMHD_PPM;
     R.c2p_maxit = p->c2p_maxit;
     R.fixup_rounds = p->fixup_max_rounds;
     R.s1 = L.s1; R.s2 = L.s2; R.vs = L.vs;
@@ -371,14 +384,19 @@ struct Engine {
     static int64_t elems(const RunDev& R, int kind, int bs) {
         const int64_t n1 = R.n1, n2 = R.n2, n3 = R.n3;
         switch (kind) {
-            case KB_BOUND: return (4 * (n2 + 2 * NG) + 4 * n1) * n3;
-            case KB_F1: case KB_F1N:
-                return R.act1 && (kind == KB_F1) == (bool)R.geo_uniform ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
-            case KB_F2: case KB_F2N:
-                return R.act2 && (kind == KB_F2) == (bool)R.geo_uniform ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
-            case KB_F3: case KB_F3N:
-                return R.act3 && (kind == KB_F3) == (bool)R.geo_uniform ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3
-                                                                         : 0;
+            case KB_BOUND: {
+                const int64_t gd = 2 + R.ppm;  // ghost layers the run fills
+                return (2 * gd * (n2 + 2 * gd) + 2 * gd * n1) * n3;
+            }
+            case KB_F1: case KB_F2: case KB_F3: case KB_F1N: case KB_F2N: case KB_F3N:
+            case KB_P1: case KB_P2: case KB_P3: case KB_P1N: case KB_P2N: case KB_P3N: {
+                const int x = kind - KB_F1, d = x % 3 + 1;
+                const bool uni = (x / 3) % 2 == 0, ppm = x >= 6;
+                if (uni != (bool)R.geo_uniform || ppm != (bool)R.ppm) return 0;
+                if (d == 1) return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
+                if (d == 2) return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
+                return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3 : 0;
+            }
             // uniform-metric update: workgroups of bs/64 waves on consecutive j (n2 padded to a
             // multiple of that)
             case KB_UPD: return R.geo_uniform ? n1 * ((n2 + bs / 64 - 1) / (bs / 64) * (bs / 64)) * n3 : 0;
@@ -444,8 +462,6 @@ struct Engine {
     int enqueue_step() {
         const int n = (int)runs.size();
         if (!n) return GRMHD_OK;
-        const int kf[4] = {0, KB_F1, KB_F2, KB_F3};
-        const int kfn[4] = {0, KB_F1N, KB_F2N, KB_F3N};
         for (int stage = 1; stage <= 2; ++stage) {
             const int which = stage - 1;
             mark(TK_BOUND);
@@ -453,12 +469,16 @@ struct Engine {
                          shape[KB_BOUND].sched, st);
             mark(TK_BOUND);
             for (int d = 1; d <= 3; ++d) {
-                if (nblk[kf[d]] <= 0 && nblk[kfn[d]] <= 0) continue;
+                int any = 0;
+                for (int v = 0; v < 4; ++v) any += nblk[flux_kind(d, v & 1, v >> 1)] > 0;
+                if (!any) continue;
                 mark(TK_FLUX1 + d - 1);
-                launch_flux(d, d_runs, boff(kf[d]), n, nblk[kf[d]], which, stage == 1, 0, 1, shape[kf[d]].bs,
-                            shape[kf[d]].sched, st);
-                launch_flux(d, d_runs, boff(kfn[d]), n, nblk[kfn[d]], which, stage == 1, 0, 0, shape[kfn[d]].bs,
-                            shape[kfn[d]].sched, st);
+                for (int v = 0; v < 4; ++v) {
+                    const bool uni = v & 1, ppm = v >> 1;
+                    const int k = flux_kind(d, uni, ppm);
+                    launch_flux(d, d_runs, boff(k), n, nblk[k], which, stage == 1, 0, uni, ppm, shape[k].bs,
+                                shape[k].sched, st);
+                }
                 mark(TK_FLUX1 + d - 1);
             }
             if (stage == 1) {
@@ -486,7 +506,9 @@ struct Engine {
     // arithmetic does not depend on the launch shape, so these are regular steps of the runs.
     int autotune(int reps, std::string* report) {
         if (runs.empty() || reps <= 0) return GRMHD_OK;
-        const int tk_of[NK] = {TK_BOUND, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_UPDATE, TK_UPDATE};
+        int tk_of[NK];
+        for (int k = 0; k < NK; ++k)
+            tk_of[k] = k == KB_BOUND ? TK_BOUND : (k >= KB_UPD ? TK_UPDATE : TK_FLUX1 + (k - KB_F1) % 3);
         double best_ms[NK];
         int best[NK];
         for (int k = 0; k < NK; ++k) { best_ms[k] = 1e300; best[k] = 0; }
@@ -913,11 +935,11 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     hipStream_t st = E.st;
     // the context's one run sits in the uniform-metric or the general table; the entropy-carrying
     // flux kernel used here reads the metric per lane and serves either
-    const int kind = R.geo_uniform ? (d == 1 ? KB_F1 : (d == 2 ? KB_F2 : KB_F3))
-                                   : (d == 1 ? KB_F1N : (d == 2 ? KB_F2N : KB_F3N));
+    const int kind = flux_kind(d, R.geo_uniform, R.ppm);
     HIPCHK(hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st));
     launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, E.shape[KB_BOUND].bs, E.shape[KB_BOUND].sched, st);
-    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, 0, E.shape[kind].bs, E.shape[kind].sched, st);
+    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, 0, R.ppm, E.shape[kind].bs, E.shape[kind].sched,
+                st);
     const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
     double* dF = nullptr;
     HIPCHK(hipMalloc(&dF, n * 8));

@@ -1,11 +1,12 @@
 // grmhd_dev.h -- device-side data layout and per-point physics of the gfx950 GR-MHD stepper.
 //
 // Layout (all FP64):
-//   cell arrays   [var][i + 2][j + 2][k]   two ghost layers in X1 and X2; X3 (phi) is periodic
-//                                           and handled by index wrap, so rows stay aligned
+//   cell arrays   [var][i + 3][j + 3][k]   three ghost layers in X1 and X2 (PPM reads three cells
+//                                           out, PLM two: a PLM run fills only two); X3 (phi) is
+//                                           periodic and handled by index wrap, so rows stay aligned
 //   face fluxes   same layout; the flux through face i-1/2 (resp. j-1/2, k-1/2) of cell (i,j,k)
 //                 is stored at (i,j,k)
-//   geometry      [component][i + 2][j + 2]  per (r, theta) point: the metric is phi-independent
+//   geometry      [component][i + 3][j + 3]  per (r, theta) point: the metric is phi-independent
 //
 // The metric of both supported coordinate systems (MKS Kerr-Schild, flat Cartesian) has
 // g_{t2} = g_{12} = g_{23} = 0 and g^{t2} = g^{t3} = g^{12} = g^{23} = 0; only the remaining
@@ -18,7 +19,7 @@ namespace grmhd {
 
 constexpr int NPR = 8;  // rho, u, u~1, u~2, u~3, B1, B2, B3
 constexpr int NCS = 9;  // sqrt(-g)(rho u^t, T^t_t, T^t_1, T^t_2, T^t_3, B1, B2, B3, S u^t)
-constexpr int NG = 2;   // ghost layers in X1 and X2
+constexpr int NG = 3;   // ghost layers in X1 and X2 held in the layout
 
 // centre geometry components
 enum {
@@ -61,12 +62,12 @@ struct RunDev {
     int32_t mks, riemann;
     int32_t c2p_maxit, fixup_rounds;
     int32_t geo_uniform;        // n3 % 64 == 0: a wave's 64 cells share (r, theta)
-    int32_t pad_;
+    int32_t ppm;                // reconstruction: 0 PLM with the MC limiter, 1 PPM
     FastDiv fd_n2, fd_n3, fd_kc;  // divisors n2, n3, n3/64 (the last only when geo_uniform)
     FastDiv fd_row[4];          // [d]: row length of the flux-face rows: n1 + 1, n2 + 1, n2 + 2 act2
     FastDiv fd_jg[3];           // [l]: number of j groups of 2^l rows, ceil(n2 / 2^l)
     int64_t s1, s2, vs;         // cell strides: i, j (k stride 1); variable stride
-    int64_t gs1, gpts;          // geometry: i stride ((n2+4)), total points
+    int64_t gs1, gpts;          // geometry: i stride (n2 + 2 NG), total points
     double dx[4], idx[4];
     double gam, cfl;
     double gg, igam1;           // (gam - 1)/gam, 1/(gam - 1)
@@ -266,6 +267,38 @@ __device__ __forceinline__ double mc_half_slope(double qm, double q0, double qp)
     const double dm = q0 - qm, dp = qp - q0, dc = qp - qm;
     const double lim = fmin(fmin(fabs(dm), fabs(dp)), 0.25 * fabs(dc));
     return (dm * dp > 0.0) ? copysign(lim, dc) : 0.0;
+}
+
+// PPM of Colella & Woodward (1984).  Edge values of the parabola in a cell of average a0 whose
+// interface values are l (lower) and r (upper), after their monotonicity constraints: a local
+// extremum gives the flat profile, and an edge value that would put the parabola's extremum inside
+// the cell is moved so that the extremum sits on the opposite edge.  The two moves exclude each
+// other, so each edge is decided on its own.
+__device__ __forceinline__ double ppm_upper_edge(double a0, double l, double r) {
+    const double da = r - l, a6 = 6.0 * (a0 - 0.5 * (l + r));
+    if ((r - a0) * (a0 - l) <= 0.0) return a0;
+    return (-da * da > da * a6) ? 3.0 * a0 - 2.0 * l : r;
+}
+__device__ __forceinline__ double ppm_lower_edge(double a0, double l, double r) {
+    const double da = r - l, a6 = 6.0 * (a0 - 0.5 * (l + r));
+    if ((r - a0) * (a0 - l) <= 0.0) return a0;
+    return (da * a6 > da * da) ? 3.0 * a0 - 2.0 * r : l;
+}
+
+// PPM states on the face between cells c and d of six consecutive cells a..f: the interface value
+// between cells j and j+1 is a_j + (a_{j+1} - a_j)/2 - (s_{j+1} - s_j)/6 with s the MC slope (here
+// from the half slopes h = s/2: (h_{j+1} - h_j)/3); the left state is the upper edge of cell c,
+// the right state the lower edge of cell d.
+__device__ __forceinline__ void ppm_face(double a, double b, double c, double d, double e, double f, double& ql,
+                                         double& qr) {
+    constexpr double third = 1.0 / 3.0;
+    const double hb = mc_half_slope(a, b, c), hc = mc_half_slope(b, c, d);
+    const double hd = mc_half_slope(c, d, e), he = mc_half_slope(d, e, f);
+    const double ibc = b + 0.5 * (c - b) - (hc - hb) * third;
+    const double icd = c + 0.5 * (d - c) - (hd - hc) * third;
+    const double ide = d + 0.5 * (e - d) - (he - hd) * third;
+    ql = ppm_upper_edge(c, ibc, icd);
+    qr = ppm_lower_edge(d, icd, ide);
 }
 
 }  // namespace grmhd

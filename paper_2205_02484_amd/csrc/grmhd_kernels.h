@@ -21,8 +21,9 @@ void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, i
                   hipStream_t st);
 // ent = 1 also computes and stores the entropy component (diagnostics); the stage chain uses 0.
 // uni = 1 (with ent = 0): the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
+// ppm = 1: the block table covers only PPM runs (0: only PLM runs)
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int uni, int bs, int sched, hipStream_t st);
+                 int ent, int uni, int ppm, int bs, int sched, hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
 // uni = 1: the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
 void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int uni, int bs,

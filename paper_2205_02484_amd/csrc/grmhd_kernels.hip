@@ -155,6 +155,7 @@ __global__ void k_geometry(GeoArgs A) {
 // boundary ghosts (Sec. 4.1): radial copy keeping sqrt(-g) B^1 with no inflow at r_out, polar
 // reflection flipping u~2 and B2; flat grids are periodic.  X3 is periodic by index wrap.
 // Each ghost is computed directly from its interior source, so one launch covers corners too.
+// A run fills as many ghost layers as its reconstruction reads: 2 for PLM, 3 for PPM.
 // ------------------------------------------------------------------------------------------
 
 __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns, int which,
@@ -165,20 +166,21 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
     if (!R.var->active) return;
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
     const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
-    const int ncolA = 4 * (n2 + 2 * NG);
-    const int64_t total = (int64_t)(ncolA + 4 * n1) * n3;
+    const int gd = 2 + R.ppm;                      // ghost layers this run reads
+    const int ncolA = 2 * gd * (n2 + 2 * gd);      // X1 ghost rows, over the X2 ghosts too
+    const int64_t total = (int64_t)(ncolA + 2 * gd * n1) * n3;
     if (e >= total) return;
     const int k = (int)(e % n3);
     const int c = (int)(e / n3);
     int i, j;
     if (c < ncolA) {
-        const int ii = c / (n2 + 2 * NG);
-        i = ii < 2 ? ii - 2 : n1 + (ii - 2);
-        j = c % (n2 + 2 * NG) - NG;
+        const int ii = c / (n2 + 2 * gd);
+        i = ii < gd ? ii - gd : n1 + (ii - gd);
+        j = c % (n2 + 2 * gd) - gd;
     } else {
         const int cc = c - ncolA;
         const int jj = cc / n1;
-        j = jj < 2 ? jj - 2 : n2 + (jj - 2);
+        j = jj < gd ? jj - gd : n2 + (jj - gd);
         i = cc % n1;
     }
     double* __restrict__ P = which ? R.Ph : R.P;
@@ -210,8 +212,8 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
 }
 
 // ------------------------------------------------------------------------------------------
-// face fluxes (Sec. 2.2): PLM/MC reconstruction of the 8 primitives, states and fluxes on both
-// sides, simplified-dispersion wave speeds, LLF (or HLL) flux, per-direction max of c_w.
+// face fluxes (Sec. 2.2): PLM/MC (or PPM) reconstruction of the 8 primitives, states and fluxes
+// on both sides, simplified-dispersion wave speeds, LLF (or HLL) flux, per-direction max of c_w.
 // ------------------------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -230,8 +232,9 @@ __device__ __forceinline__ constexpr int flux_store_slot(int q) {
 // conserved vector, flux and speeds are finished before the right state is formed, which keeps
 // the live register set to one state plus two flux vectors.  With ENT = false the entropy
 // component (read only by the entropy inversion of the slow path, which recomputes it for its
-// own faces) is neither computed nor stored: that saves both powers of rho per face.
-template <int D, bool UNI, bool ENT>
+// own faces) is neither computed nor stored: that saves both powers of rho per face.  PPM reads
+// three cells on each side of the face (PLM two), which the run's ghost layers cover.
+template <int D, bool UNI, bool ENT, bool PPM>
 __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k, int which, double* ent_out) {
     constexpr int NQ = ENT ? NCS : 8;
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
@@ -254,14 +257,22 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         return 0.0;
     }
     const double* __restrict__ P = which ? R.Ph : R.P;
-    int64_t cm2, cm1, cp1;
-    if (D == 1) { cm2 = ci - 2 * R.s1; cm1 = ci - R.s1; cp1 = ci + R.s1; }
-    else if (D == 2) { cm2 = ci - 2 * R.s2; cm1 = ci - R.s2; cp1 = ci + R.s2; }
-    else {
+    int64_t cm3 = 0, cm2, cm1, cp1, cp2 = 0;
+    if (D == 1) {
+        cm2 = ci - 2 * R.s1; cm1 = ci - R.s1; cp1 = ci + R.s1;
+        if (PPM) { cm3 = ci - 3 * R.s1; cp2 = ci + 2 * R.s1; }
+    } else if (D == 2) {
+        cm2 = ci - 2 * R.s2; cm1 = ci - R.s2; cp1 = ci + R.s2;
+        if (PPM) { cm3 = ci - 3 * R.s2; cp2 = ci + 2 * R.s2; }
+    } else {
         const int64_t base = ci - k;
         cm2 = base + (k >= 2 ? k - 2 : k - 2 + n3);
         cm1 = base + (k >= 1 ? k - 1 : k - 1 + n3);
         cp1 = base + (k + 1 < n3 ? k + 1 : k + 1 - n3);
+        if (PPM) {  // n3 >= 3 for PPM runs (checked when a run is created)
+            cm3 = base + (k >= 3 ? k - 3 : k - 3 + n3);
+            cp2 = base + (k + 2 < n3 ? k + 2 : k + 2 - n3);
+        }
     }
     double Pl[NPR], Pr[NPR];
 #pragma unroll
@@ -269,8 +280,12 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         const double* Pq = P + q * R.vs;
         const double a = gld(Pq, (uint32_t)cm2), b = gld(Pq, (uint32_t)cm1), c = gld(Pq, (uint32_t)ci),
                      d = gld(Pq, (uint32_t)cp1);
-        Pl[q] = b + mc_half_slope(a, b, c);
-        Pr[q] = c - mc_half_slope(b, c, d);
+        if (PPM) {
+            ppm_face(gld(Pq, (uint32_t)cm3), a, b, c, d, gld(Pq, (uint32_t)cp2), Pl[q], Pr[q]);
+        } else {
+            Pl[q] = b + mc_half_slope(a, b, c);
+            Pr[q] = c - mc_half_slope(b, c, d);
+        }
     }
     if (!UNI) load_geo(D == 3 ? R.gc : R.gf[D], R.gpts, geo_index(R, i, j), G);
     const double gam = R.gam;
@@ -325,11 +340,12 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
 template <int D>
 __device__ __forceinline__ double entropy_flux(const RunDev& R, int i, int j, int k, int which) {
     double f = 0.0;
-    flux_face<D, false, true>(R, i, j, k, which, &f);
+    if (R.ppm) flux_face<D, false, true, true>(R, i, j, k, which, &f);
+    else flux_face<D, false, true, false>(R, i, j, k, which, &f);
     return f;
 }
 
-template <int D, bool ENT, bool UNI>
+template <int D, bool ENT, bool UNI, bool PPM>
 __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                               int nruns, int which, int do_cfl, int sched) {
     const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -368,7 +384,7 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
             i = (int)q + i0;
             j = (int)(row - q * (uint32_t)nj) + j0;
         }
-        cw = flux_face<D, UNI, ENT>(R, i, j, (int)k, which, nullptr);
+        cw = flux_face<D, UNI, ENT, PPM>(R, i, j, (int)k, which, nullptr);
     }
     if (!do_cfl) return;
     __shared__ double red[4];
@@ -1057,21 +1073,26 @@ void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, i
     if (nblocks > 0) k_bound<<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, sched);
 }
 
+template <bool ENT, bool UNI, bool PPM>
+static void flux_dir(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
+                     int bs, int sched, hipStream_t st) {
+    if (d == 1) k_flux<1, ENT, UNI, PPM><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+    else if (d == 2) k_flux<2, ENT, UNI, PPM><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+    else k_flux<3, ENT, UNI, PPM><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+}
+
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int uni, int bs, int sched, hipStream_t st) {
+                 int ent, int uni, int ppm, int bs, int sched, hipStream_t st) {
     if (nblocks <= 0) return;
     if (ent) {
-        if (d == 1) k_flux<1, true, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else if (d == 2) k_flux<2, true, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else k_flux<3, true, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        if (ppm) flux_dir<true, false, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
+        else flux_dir<true, false, false>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
     } else if (uni) {
-        if (d == 1) k_flux<1, false, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else if (d == 2) k_flux<2, false, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else k_flux<3, false, true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        if (ppm) flux_dir<false, true, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
+        else flux_dir<false, true, false>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
     } else {
-        if (d == 1) k_flux<1, false, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else if (d == 2) k_flux<2, false, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else k_flux<3, false, false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        if (ppm) flux_dir<false, false, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
+        else flux_dir<false, false, false>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
     }
 }
 

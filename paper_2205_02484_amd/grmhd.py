@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgrmhd.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EAGAIN, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 MKS, MINKOWSKI_CART = 0, 1
 LLF, HLL = 0, 1
+PLM, PPM = 0, 1
 
 # exported symbols of include/grmhd.h
 SYMBOLS = [
@@ -45,7 +46,7 @@ class Horizon(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("spin", ctypes.c_double), ("gam", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("riemann", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("riemann", ctypes.c_int32), ("recon", ctypes.c_int32),
                 ("rho_fl_coef", ctypes.c_double), ("rho_fl_pow", ctypes.c_double),
                 ("u_fl_coef", ctypes.c_double), ("u_fl_pow", ctypes.c_double), ("fl_abs", ctypes.c_double),
                 ("bsq_rho_max", ctypes.c_double), ("bsq_u_max", ctypes.c_double),
@@ -148,6 +149,8 @@ def make_params(cfg, **over) -> Params:
     p.cfl = float(get("cfl", p.cfl))
     r = get("riemann", "llf")
     p.riemann = HLL if r in ("hll", HLL) else LLF
+    rec = get("recon", "plm")
+    p.recon = PPM if rec in ("ppm", PPM) else PLM
     for name in ("rho_fl_coef", "rho_fl_pow", "u_fl_coef", "u_fl_pow", "fl_abs", "bsq_rho_max",
                  "bsq_u_max", "gamma_max", "beta_entropy", "c2p_tol"):
         setattr(p, name, float(get(name, getattr(p, name))))

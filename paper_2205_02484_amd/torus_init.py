@@ -59,6 +59,7 @@ class TorusConfig:
     field: bool = True
     r_br: float = 0.0              # > 0: radius where r(X1) turns hyper-exponential
     n_x: int = 4                   # power of the hyper-exponential term
+    recon: str = "plm"             # face reconstruction: "plm" (MC limiter) or "ppm"
 
     @property
     def r_horizon(self) -> float:
