@@ -69,7 +69,7 @@ typedef struct {
     double xmin[3], xmax[3];        /* flat Cartesian test grids */
     double a, gam, cfl;
     int32_t riemann;
-    int32_t pad0;
+    int32_t pole_fix;               /* MKS: u~2 of this many cells next to each pole interpolated to 0 (Sec. 4.1) */
     double rho_fl_coef, rho_fl_pow, u_fl_coef, u_fl_pow, fl_abs;
     double bsq_rho_max, bsq_u_max, gamma_max, beta_entropy;
     double c2p_tol;
@@ -659,6 +659,7 @@ static int grid_init(Grid* g, const orc_cfg* c) {
     g->c = c;
     g->n[1] = c->n1; g->n[2] = c->n2; g->n[3] = c->n3;
     if (c->recon != 0 && c->recon != 1) return -1;
+    if (c->pole_fix < 0 || (c->pole_fix > 0 && (c->coords != ORC_MKS || 2 * c->pole_fix >= c->n2))) return -1;
     for (int d = 1; d <= 3; d++) {
         if (g->n[d] < 1) return -1;
         g->active[d] = g->n[d] > 1;
@@ -720,10 +721,26 @@ static void store_interior(const Grid* g, const double* P, double* out, int nv) 
 
 static void copy_cell(double* dst, const double* src) { memcpy(dst, src, NPR * sizeof(double)); }
 
+/* Polar u~2 interpolation (Sec. 4.1, READING-24): in the np cells next to each pole the polar
+ * velocity component is replaced by the straight line in X2 from zero at the pole to its value at
+ * the centre of the first cell left alone (j = np, resp. n2-1-np).  In Kerr-Schild g^{t2} = 0, so
+ * u~2 is u^2 itself.  Applied to the interior before the ghosts are filled. */
+static void pole_fix(const Grid* g, double* P) {
+    int n1 = g->n[1], n2 = g->n[2], n3 = g->n[3], np = g->c->pole_fix;
+    for (int i = 0; i < n1; i++)
+        for (int k = 0; k < n3; k++)
+            for (int j = 0; j < np; j++) {
+                double f = (j + 0.5) / (np + 0.5);   /* distance to the pole over the reference's */
+                P[cidx(g, i, j, k) * NPR + 3] = P[cidx(g, i, np, k) * NPR + 3] * f;
+                P[cidx(g, i, n2 - 1 - j, k) * NPR + 3] = P[cidx(g, i, n2 - 1 - np, k) * NPR + 3] * f;
+            }
+}
+
 static void bound(const Grid* g, double* P) {
     const orc_cfg* c = g->c;
     int n1 = g->n[1], n2 = g->n[2], n3 = g->n[3];
     int g1 = g->g[1], g2 = g->g[2], g3 = g->g[3];
+    if (c->coords == ORC_MKS && c->pole_fix > 0) pole_fix(g, P);
     if (c->coords == ORC_MKS) {
         /* X1: copy the nearest active cell, keep sqrt(-g) B^1, no inflow at the outer edge */
         for (int j = 0; j < n2; j++)

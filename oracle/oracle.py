@@ -27,7 +27,7 @@ class OrcCfg(ctypes.Structure):
         ("r_in", ctypes.c_double), ("r_out", ctypes.c_double), ("h", ctypes.c_double),
         ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3),
         ("a", ctypes.c_double), ("gam", ctypes.c_double), ("cfl", ctypes.c_double),
-        ("riemann", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("riemann", ctypes.c_int32), ("pole_fix", ctypes.c_int32),
         ("rho_fl_coef", ctypes.c_double), ("rho_fl_pow", ctypes.c_double),
         ("u_fl_coef", ctypes.c_double), ("u_fl_pow", ctypes.c_double), ("fl_abs", ctypes.c_double),
         ("bsq_rho_max", ctypes.c_double), ("bsq_u_max", ctypes.c_double),
@@ -124,6 +124,7 @@ def make_cfg(obj=None, **over) -> OrcCfg:
     c.n_x = int(get("n_x", 4))
     rec = get("recon", "plm")
     c.recon = 1 if rec in ("ppm", 1) else 0
+    c.pole_fix = int(get("pole_fix", 0))
     return c
 
 
