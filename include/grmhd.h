@@ -65,7 +65,13 @@ typedef struct {
      * (EINVAL unless r_br > r_in and 2 <= n_x <= 16 when r_br > 0).  X1 spans [ln r_in, X1_out]
      * with r(X1_out) = r_out in n1 equal cells. */
     double r_br;
-    int32_t n_x, reserved_;
+    int32_t n_x;
+    /* MKS polar velocity interpolation (Sec. 4.1, boundary conditions): in the pole_fix cells
+     * next to each pole, u~2 is replaced by the straight line in X2 from zero at the pole to its
+     * value at the centre of cell pole_fix (resp. n2-1-pole_fix), in each stage's input before the
+     * ghosts are filled.  0 (default) turns it off; the paper uses 2.  EINVAL unless
+     * 0 <= pole_fix and 2 pole_fix < n2, and pole_fix = 0 on flat grids. */
+    int32_t pole_fix;
 } grmhd_grid;
 
 /* Physics and numerics.  Defaults (grmhd_params_default) are the paper's values: cfl 0.45

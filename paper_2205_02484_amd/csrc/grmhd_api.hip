@@ -141,7 +141,10 @@ int validate(const grmhd_grid* g, const grmhd_params* p) {
         if (!(std::fabs(p->spin) < 1.0)) return fail(GRMHD_EINVAL, "|spin| must be < 1");
         if (g->r_br > 0.0 && (!(g->r_br > g->r_in) || g->n_x < 2 || g->n_x > 16))
             return fail(GRMHD_EINVAL, "hyper-exponential map needs r_br > r_in and 2 <= n_x <= 16");
+        if (g->pole_fix < 0 || 2 * (int64_t)g->pole_fix >= g->n2)
+            return fail(GRMHD_EINVAL, "pole_fix needs 0 <= pole_fix and 2 pole_fix < n2");
     } else {
+        if (g->pole_fix != 0) return fail(GRMHD_EINVAL, "pole_fix applies to MKS grids only");
         for (int d = 0; d < 3; ++d)
             if (!(g->xmax[d] > g->xmin[d])) return fail(GRMHD_EINVAL, "need xmin < xmax");
     }
@@ -235,6 +238,7 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.mks = g->coords == GRMHD_MKS;
     R.riemann = p->riemann;
     R.ppm = p->recon == GRMHD_PPM;
+    R.pole_fix = R.mks ? g->pole_fix : 0;
     R.c2p_maxit = p->c2p_maxit;
     R.fixup_rounds = p->fixup_max_rounds;
     R.s1 = L.s1; R.s2 = L.s2; R.vs = L.vs;
@@ -386,7 +390,7 @@ struct Engine {
         switch (kind) {
             case KB_BOUND: {
                 const int64_t gd = 2 + R.ppm;  // ghost layers the run fills
-                return (2 * gd * (n2 + 2 * gd) + 2 * gd * n1) * n3;
+                return (2 * gd * (n2 + 2 * gd) + 2 * gd * n1 + 2 * (int64_t)R.pole_fix * n1) * n3;
             }
             case KB_F1: case KB_F2: case KB_F3: case KB_F1N: case KB_F2N: case KB_F3N:
             case KB_P1: case KB_P2: case KB_P3: case KB_P1N: case KB_P2N: case KB_P3N: {

@@ -63,6 +63,8 @@ struct RunDev {
     int32_t c2p_maxit, fixup_rounds;
     int32_t geo_uniform;        // n3 % 64 == 0: a wave's 64 cells share (r, theta)
     int32_t ppm;                // reconstruction: 0 PLM with the MC limiter, 1 PPM
+    int32_t pole_fix;           // MKS: cells next to each pole whose u~2 is interpolated to zero
+    int32_t pad_;
     FastDiv fd_n2, fd_n3, fd_kc;  // divisors n2, n3, n3/64 (the last only when geo_uniform)
     FastDiv fd_row[4];          // [d]: row length of the flux-face rows: n1 + 1, n2 + 1, n2 + 2 act2
     FastDiv fd_jg[3];           // [l]: number of j groups of 2^l rows, ceil(n2 / 2^l)

@@ -155,7 +155,11 @@ __global__ void k_geometry(GeoArgs A) {
 // boundary ghosts (Sec. 4.1): radial copy keeping sqrt(-g) B^1 with no inflow at r_out, polar
 // reflection flipping u~2 and B2; flat grids are periodic.  X3 is periodic by index wrap.
 // Each ghost is computed directly from its interior source, so one launch covers corners too.
-// A run fills as many ghost layers as its reconstruction reads: 2 for PLM, 3 for PPM.
+// A run fills as many ghost layers as its reconstruction reads: 2 for PLM, 3 for PPM.  With the
+// polar velocity interpolation on (pole_fix = n_p > 0, MKS), u~2 of the n_p interior cells next
+// to each pole becomes the straight line in X2 from zero at the pole to the centre of the first
+// cell left alone; the same launch writes those cells, and every ghost whose source is one of them
+// computes that value from the reference cell itself, so no thread reads a cell being written.
 // ------------------------------------------------------------------------------------------
 
 __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns, int which,
@@ -167,11 +171,26 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
     const int64_t e = (int64_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
     const int gd = 2 + R.ppm;                      // ghost layers this run reads
+    const int npf = R.pole_fix;                    // 0 unless MKS with the polar interpolation
     const int ncolA = 2 * gd * (n2 + 2 * gd);      // X1 ghost rows, over the X2 ghosts too
-    const int64_t total = (int64_t)(ncolA + 2 * gd * n1) * n3;
+    const int ncolB = 2 * gd * n1;                 // X2 ghost rows
+    const int64_t total = (int64_t)(ncolA + ncolB + 2 * npf * n1) * n3;
     if (e >= total) return;
     const int k = (int)(e % n3);
     const int c = (int)(e / n3);
+    double* __restrict__ P = which ? R.Ph : R.P;
+    if (c >= ncolA + ncolB) {
+        // interior cell next to a pole: u~2 = (m + 1/2)/(n_p + 1/2) times u~2 of the reference cell
+        const int cc = c - ncolA - ncolB;
+        const int jj = cc / n1, i = cc % n1;      // jj < 2 n_p
+        const bool upper = jj >= npf;
+        const int m = upper ? jj - npf : jj;      // cells between this one and the pole
+        const int j = upper ? n2 - 1 - m : m;
+        const int jr = upper ? n2 - 1 - npf : npf;
+        const double f = ((double)m + 0.5) / ((double)npf + 0.5);
+        gst(P + 3 * R.vs, (uint32_t)cell_index(R, i, j, k), gld(P + 3 * R.vs, (uint32_t)cell_index(R, i, jr, k)) * f);
+        return;
+    }
     int i, j;
     if (c < ncolA) {
         const int ii = c / (n2 + 2 * gd);
@@ -183,7 +202,6 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
         j = jj < gd ? jj - gd : n2 + (jj - gd);
         i = cc % n1;
     }
-    double* __restrict__ P = which ? R.Ph : R.P;
     int is, js;
     if (R.mks) {
         is = i < 0 ? 0 : (i >= n1 ? n1 - 1 : i);
@@ -193,9 +211,17 @@ __global__ void k_bound(const RunDev* __restrict__ runs, const int* __restrict__
         js = (j + n2) % n2;
     }
     const int64_t src = cell_index(R, is, js, k), dst = cell_index(R, i, j, k);
+    // a source next to a pole has its u~2 rewritten by this launch: take it from the reference
+    const int mp = npf == 0 ? -1 : (js < npf ? js : (js >= n2 - npf ? n2 - 1 - js : -1));
     double v[NPR];
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) v[q] = gld(P + q * R.vs, (uint32_t)src);
+    for (int q = 0; q < NPR; ++q)
+        if (q != 3 || mp < 0) v[q] = gld(P + q * R.vs, (uint32_t)src);
+    if (mp >= 0) {
+        const int jr = js < npf ? npf : n2 - 1 - npf;
+        const double f = ((double)mp + 0.5) / ((double)npf + 0.5);
+        v[3] = gld(P + 3 * R.vs, (uint32_t)cell_index(R, is, jr, k)) * f;
+    }
     if (R.mks) {
         if (i != is) {
             const int64_t np = R.gpts;

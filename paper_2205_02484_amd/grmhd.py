@@ -35,7 +35,7 @@ class Grid(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
                 ("coords", ctypes.c_int32), ("r_in", ctypes.c_double), ("r_out", ctypes.c_double),
                 ("h", ctypes.c_double), ("xmin", ctypes.c_double * 3), ("xmax", ctypes.c_double * 3),
-                ("r_br", ctypes.c_double), ("n_x", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("r_br", ctypes.c_double), ("n_x", ctypes.c_int32), ("pole_fix", ctypes.c_int32)]
 
 
 class Horizon(ctypes.Structure):
@@ -136,6 +136,7 @@ def make_grid(cfg, **over) -> Grid:
         g.xmin[d], g.xmax[d] = float(xmin[d]), float(xmax[d])
     g.r_br = float(get("r_br", 0.0) or 0.0)
     g.n_x = int(get("n_x", 4))
+    g.pole_fix = int(get("pole_fix", 0))
     return g
 
 

@@ -60,6 +60,7 @@ class TorusConfig:
     r_br: float = 0.0              # > 0: radius where r(X1) turns hyper-exponential
     n_x: int = 4                   # power of the hyper-exponential term
     recon: str = "plm"             # face reconstruction: "plm" (MC limiter) or "ppm"
+    pole_fix: int = 0              # cells next to each pole whose u~2 is interpolated to 0 (paper: 2)
 
     @property
     def r_horizon(self) -> float:
