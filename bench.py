@@ -27,7 +27,9 @@ sys.path.insert(0, ROOT)
 ALG_BYTES = {"flux1": 120.0, "flux2": 120.0, "flux3": 120.0, "update": 329.0, "bound": 128.0}
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256.json")
+# committed rocprofv3 counters of the 256^3 workload, per face reconstruction
+COUNTERS = {"plm": os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256.json"),
+            "ppm": os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256_ppm.json")}
 
 
 def kernel_source_hash():
@@ -39,20 +41,22 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profiled_counters(workload):
+def profiled_counters(workload, recon):
     """Per-launch HBM bytes and FP64 FLOP of the committed rocprofv3 passes, or None when the
     kernels have changed since they were taken (source hash) or the workload differs."""
     try:
-        with open(COUNTERS) as fh:
+        with open(COUNTERS[recon]) as fh:
             js = json.load(fh)
     except OSError:
         return None
-    if js.get("workload") != workload or js.get("kernel_source_sha256") != kernel_source_hash():
+    if js.get("workload") != workload or js.get("recon", "plm") != recon:
+        return None
+    if js.get("kernel_source_sha256") != kernel_source_hash():
         return None
     return js["per_launch"]
 
 
-def units_per_launch(kind, n1, n2, n3):
+def units_per_launch(kind, n1, n2, n3, recon="plm"):
     if kind == "flux1":
         return (n1 + 1) * (n2 + 2) * n3
     if kind == "flux2":
@@ -62,7 +66,8 @@ def units_per_launch(kind, n1, n2, n3):
     if kind == "update":
         return n1 * n2 * n3
     if kind == "bound":
-        return (4 * (n2 + 4) + 4 * n1) * n3
+        g = 3 if recon == "ppm" else 2     # ghost layers a run fills
+        return (2 * g * (n2 + 2 * g) + 2 * g * n1) * n3
     return 0
 
 
@@ -121,6 +126,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="torus3d_256x256x256")
+    ap.add_argument("--recon", choices=("plm", "ppm"), default="plm",
+                    help="face reconstruction: PLM with the MC limiter (the paper's) or PPM")
     ap.add_argument("--cpu-steps", type=int, default=5, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble and served-stream legs")
@@ -155,6 +162,7 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     cfg = WORKLOADS[args.workload]()
+    cfg.recon = args.recon
     P = make_torus(cfg)
     n1, n2, n3 = cfg.n1, cfg.n2, cfg.n3
     zones = n1 * n2 * n3
@@ -190,9 +198,9 @@ def main():
     tot = {k: v[0] * v[1] for k, v in kt.items()}
     dom = max((k for k in tot if k in ALG_BYTES), key=lambda k: tot[k])
     avg_ms = kt[dom][0]
-    units = units_per_launch(dom, n1, n2, n3)
+    units = units_per_launch(dom, n1, n2, n3, args.recon)
     achieved = ALG_BYTES[dom] * units / (avg_ms * 1e-3) / 1e9
-    prof = profiled_counters(args.workload)
+    prof = profiled_counters(args.workload, args.recon)
     traffic = None
     if prof and dom in prof:
         traffic = prof[dom]["hbm_read_bytes"] + prof[dom]["hbm_write_bytes"]
@@ -225,7 +233,7 @@ def main():
         "data": "synthetic (seeded Fishbone-Moncrief torus, 4% u perturbation, beta_0 = 100)",
         "config": {"workload": args.workload, "grid": [n1, n2, n3], "zones": zones, "spin": cfg.spin,
                    "gamma": cfg.gam, "r_out": cfg.r_out, "r_in_torus": cfg.r_in, "r_max": cfg.r_max,
-                   "cfl": cfg.cfl, "riemann": "llf"},
+                   "cfl": cfg.cfl, "riemann": "llf", "recon": args.recon},
         "roofline": roofline,
         "kernels": kernels,
         "autotune": [ln for ln in (tuned or "").splitlines() if ln.startswith("chosen")],
