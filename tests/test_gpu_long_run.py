@@ -1,7 +1,8 @@
 """The 128x64x64 torus (r_out = 200, gamma = 13/9, beta_0 = 100, 4 per cent perturbation) advanced
-1000 RK2 steps at CFL 0.45 on the GPU, in the graph-replayed launch chain: the state stays finite
-with no cell left unfixed, the corner divergence of sqrt(-g) B that flux-CT preserves (Sec. 2.2)
-stays at round-off, and the torus is still in place.  There is no oracle run at this length (the
+1000 RK2 steps at CFL 0.45 on the GPU, in the graph-replayed launch chain, with PLM and with PPM
+plus the polar u~2 interpolation: the state stays finite with no cell left unfixed, the corner
+divergence of sqrt(-g) B that flux-CT preserves (Sec. 2.2) stays at round-off, and the torus is
+still in place.  There is no oracle run at this length (the
 CPU would need minutes); the properties checked hold for any correct step.
 """
 import math
@@ -28,8 +29,11 @@ def G():
     return grmhd
 
 
-def test_thousand_steps_128x64x64_stable_and_divergence_free(G):
+@pytest.mark.parametrize("variant", ["plm", "ppm_polefix"])
+def test_thousand_steps_128x64x64_stable_and_divergence_free(G, variant):
     c = torus_128x64x64()
+    if variant == "ppm_polefix":
+        c.recon, c.pole_fix = "ppm", 2
     P0 = make_torus(c)
     cfg = orc.make_cfg(c)
     gd = _centre_gdet(cfg)[..., None]
@@ -48,7 +52,7 @@ def test_thousand_steps_128x64x64_stable_and_divergence_free(G):
     P1 = ctx.get_prims()
     mdot, phib = ctx.diag()
     ctx.close()
-    print(f"1000 steps of 128x64x64: t = {t:.3f} M, {999 * c.n1 * c.n2 * c.n3 / el:.3e} zone-updates/s")
+    print(f"1000 steps of 128x64x64 ({variant}): t = {t:.3f} M, {999 * c.n1 * c.n2 * c.n3 / el:.3e} zone-updates/s")
 
     assert nstep == 1000 and t > 0.0
     assert np.isfinite(P1).all()
