@@ -17,12 +17,14 @@
  *   conservative fluxes incl. entropy                          Sec. 2.1, conservative form
  *   finite-volume update, centred geometric source             Sec. 2.2 (Numerical discretization)
  *   PLM with the MC limiter                                    Sec. 2.2, limiter cases
+ *   PPM (Colella & Woodward 1984), the upgrade Sec. 2.2 names  their Eqs. 1.6-1.8 and 1.10
  *   Lax-Friedrichs and HLL fluxes, simplified dispersion       Sec. 2.2, Eqs. fluxes_riemann/HLL
  *   flux-CT                                                    Sec. 2.2, Eq. fluxCT_F1 and E^1
  *   RK2 midpoint step and CFL time step                        Sec. 2.2, end
  *   conserved-to-primitive inversion and fixups                Sec. 2.3
  *   floors, magnetisation ceilings, Lorentz cap                Sec. 2.4 (Flooring model)
  *   Kerr-Schild metric, MKS coordinates, boundary conditions   Sec. 4.1
+ *   hyper-exponential radial map, polar u~2 interpolation      Sec. 4.1
  *   horizon mass accretion rate and magnetic flux              Sec. 4.2, Eqs. diag_Mdot, diag_MAD
  *   angular momentum and energy fluxes, radial profiles of the
  *   mass flux and of the inward/outward angular momentum flux  Sec. 4.2, Eqs.
@@ -46,6 +48,14 @@
  *  19  horizon index: first cell centre with r >= r_h; signed Mdot
  *  20  negative discriminant clamped to 0; HLL 0/0 falls back to the central average
  *  21  NR: 50 iterations max; Brent: bracket [D, 2^n W_hi], converged to 4 eps relative
+ *  22  radial map: R_0 = 0, break at r_br, outer X1 edge where r = r_out (bisection)
+ *  23  PPM variant: Colella & Woodward 1984 on the primitives, no steepening or flattening
+ *  24  polar u~2: straight line in X2 to zero at the pole from the first cell left alone,
+ *      on each stage input before the ghosts are filled
+ *
+ * Parity unpinned: the radial ghost treatment of READING-12 (bound()).  Flux-CT keeps the
+ * corner divergence whatever the ghost values are and no closed form covers inflow/outflow
+ * ghosts, so only agreement between this file and the GPU path checks it.
  */
 #include <complex.h>
 #include <float.h>
