@@ -383,9 +383,13 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     const int j0 = D == 2 ? 0 : -R.act2;
     const int ni = D == 1 ? n1 + 1 : n1 + 2 * R.act1;
     const int nj = D == 2 ? n2 + 1 : n2 + 2 * R.act2;
-    // rows of n3 faces, ordered so that neighbouring rows along the stencil direction are
-    // consecutive (X1 faces: i fastest; X2 and X3 faces: j fastest).  Every index fits 31 bits
-    // (checked when a run is created); divisions use the run's precomputed multipliers.
+    // rows of n3 faces.  With n3 % 64 == 0 a wave is one row, and X1-face rows go i fastest so
+    // that the stencil planes are read close together in time; otherwise a wave spans several
+    // rows, and every direction goes j fastest, since consecutive j rows are adjacent in memory
+    // (i-fastest rows would spread a wave over planes ~(n2+6) n3 doubles apart: with n3 = 1 every
+    // lane of a load touches its own cache line).  X2 and X3 faces always go j fastest.  Every
+    // index fits 31 bits (checked when a run is created); divisions use the run's precomputed
+    // multipliers.
     const uint32_t nrows = (uint32_t)ni * (uint32_t)nj;
     uint32_t row, k;
     if (UNI) {
@@ -401,9 +405,11 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     }
     double cw = 0.0;
     if (row < nrows) {
-        const uint32_t q = fdiv(row, R.fd_row[D]);
+        constexpr bool IFAST = D == 1 && UNI;
+        // fd_row[3] divides by n2 + 2 act2, the X1-face row length in j
+        const uint32_t q = fdiv(row, (D == 1 && !UNI) ? R.fd_row[3] : R.fd_row[D]);
         int i, j;
-        if (D == 1) {
+        if (IFAST) {
             j = (int)q + j0;
             i = (int)(row - q * (uint32_t)ni) + i0;
         } else {
