@@ -166,7 +166,8 @@ int grmhd_debug_fluxes(grmhd_ctx* ctx, int32_t d, double* F, double* cmax);
  * in/out) is a stage output whose cells with code[] == -1 failed (their values are not read),
  * `pin` the stage input; code[] (host, in/out, values -1..3) marks the failed cells.  The device
  * fixup kernel runs its Jacobi rounds (at most params.fixup_max_rounds): on return pout holds the
- * fixed state (floors applied to fixed cells; cells left unfixed carry their pin values), code[]
+ * fixed state (floors applied to fixed cells; cells left unfixed carry the pin values of rho, u and
+ * u~ and keep the pout field, which the flux-CT update produced), code[]
  * is 3 for cells fixed by averaging and still -1 for cells left unfixed, *left (nullable) counts
  * those.  The context's state becomes the returned pout.  Diagnostic entry point for fixup
  * parity; EINVAL on NULL pointers, NaN in pin or codes outside -1..3. */

@@ -41,7 +41,8 @@
  *  10  floors as printed (exponent -1/2 on rho) unless the run sets other coefficients
  *  12  radial BC: copy, keep sqrt(-g) B^1, u~1 >= 0 at the outer edge; polar BC: mirror
  *  13  CFL: global per-direction minimum, harmonic sum, from the stage-1 face speeds
- *  14  fixups: deterministic Jacobi rounds, outside neighbours invalid, any-valid fallback
+ *  14  fixups: deterministic Jacobi rounds, outside neighbours invalid, any-valid fallback;
+ *      a cell left unfixed takes rho, u, u~ from the stage input and keeps its updated field
  *  15  ceilings: add mass/energy at rest in the normal frame, re-invert with the energy
  *      equation only, else add them in the fluid frame
  *  16  2D keeps E^3 only; polar X2 fluxes and polar-edge EMFs are zero
@@ -53,9 +54,12 @@
  *  24  polar u~2: straight line in X2 to zero at the pole from the first cell left alone,
  *      on each stage input before the ghosts are filled
  *
- * Parity unpinned: the radial ghost treatment of READING-12 (bound()).  Flux-CT keeps the
- * corner divergence whatever the ghost values are and no closed form covers inflow/outflow
- * ghosts, so only agreement between this file and the GPU path checks it.
+ * Pins (tests/test_oracle_*.py) fix every part against the mathematics rather than against the
+ * GPU path.  The radial ghosts of READING-12 are pinned by consequences: a monopole field stays
+ * divergence-free through them; exact marginally bound radial dust with a monopole (infall
+ * through the inner edge inside the horizon, a supersonic wind through the outer edge) converges
+ * in the edge cells; the outer clamp blocks inflow.  The HLL weights are pinned by their
+ * one-sided and symmetric limits.  Planted mistakes in copies of this file fail those pins.
  */
 #include <complex.h>
 #include <float.h>
@@ -1068,12 +1072,15 @@ static long fixups(const Grid* g, double* Pout, const double* Pin, signed char* 
                     }
     }
     free(pend);
+    /* A cell left unfixed keeps the stage input's rho, u and u~ and the field the stage produced:
+     * Sec. 2.3 fixes only the fluid variables, and the field comes from the flux-CT update, so
+     * taking the input's field instead would break the corner divergence around the cell. */
     long left = 0;
     for (int i = 0; i < n1; i++)
         for (int j = 0; j < n2; j++)
             for (int k = 0; k < n3; k++)
                 if (code[cidx(g, i, j, k)] < 0) {
-                    memcpy(&Pout[cidx(g, i, j, k) * NPR], &Pin[cidx(g, i, j, k) * NPR], NPR * sizeof(double));
+                    memcpy(&Pout[cidx(g, i, j, k) * NPR], &Pin[cidx(g, i, j, k) * NPR], 5 * sizeof(double));
                     left++;
                 }
     return left;
@@ -1190,6 +1197,28 @@ int orc_step(const orc_cfg* c, double* P, int nsteps, double dt_fixed, double* d
         (void)nn;
     }
     if (nfail) *nfail = fails;
+    work_free(&w);
+    return 0;
+}
+
+/* The interior state with its boundary ghosts filled as a stage fills them (Sec. 4.1, READING-12
+ * and READING-24), written out with the ghost layers as [8][N1][N2][N3], N = n + 2 g (g = 2 for
+ * PLM, 3 for PPM, 0 in an inactive direction).  Lets the tests check the boundary treatment on
+ * its own. */
+int orc_ghosts(const orc_cfg* c, const double* Pint, double* out) {
+    Work w;
+    int rc = work_init(&w, c);
+    if (rc) { work_free(&w); return rc; }
+    load_interior(&w.g, Pint, w.Pn);
+    bound(&w.g, w.Pn);
+    const Grid* g = &w.g;
+    size_t nn = ncells(g);
+    for (int i = -g->g[1]; i < g->n[1] + g->g[1]; i++)
+        for (int j = -g->g[2]; j < g->n[2] + g->g[2]; j++)
+            for (int k = -g->g[3]; k < g->n[3] + g->g[3]; k++) {
+                size_t ci = cidx(g, i, j, k);
+                for (int v = 0; v < NPR; v++) out[v * nn + ci] = w.Pn[ci * NPR + v];
+            }
     work_free(&w);
     return 0;
 }

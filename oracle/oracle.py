@@ -50,31 +50,68 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def _load(path):
+    L = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    cp = ctypes.POINTER(OrcCfg)
+    bp = ctypes.POINTER(ctypes.c_int8)
+    L.orc_step.argtypes = [cp, dp, ctypes.c_int, ctypes.c_double, dp, ctypes.POINTER(ctypes.c_int64), bp]
+    L.orc_fluxes.argtypes = [cp, dp, ctypes.c_int, dp, dp]
+    L.orc_prim2cons.argtypes = [cp, dp, dp]
+    L.orc_cons2prim.argtypes = [cp, dp, dp, bp]
+    L.orc_diag.argtypes = [cp, dp, dp, dp]
+    L.orc_diag_full.argtypes = [cp, dp, dp, dp, dp]
+    L.orc_grid_x1.argtypes = [cp, dp, dp]
+    L.orc_ppm_face.argtypes = [dp, dp, dp]
+    L.orc_geom.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
+    L.orc_point_state.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp] + [dp] * 10
+    L.orc_point_c2p.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
+    L.orc_point_floors.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp]
+    L.orc_mc_slope.argtypes = [ctypes.c_double] * 3
+    L.orc_mc_slope.restype = ctypes.c_double
+    L.orc_ghosts.argtypes = [cp, dp, dp]
+    L.orc_fixups.restype = ctypes.c_int64
+    L.orc_fixups.argtypes = [cp, dp, dp, bp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
             build(force=True)
-        L = ctypes.CDLL(LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        cp = ctypes.POINTER(OrcCfg)
-        bp = ctypes.POINTER(ctypes.c_int8)
-        L.orc_step.argtypes = [cp, dp, ctypes.c_int, ctypes.c_double, dp, ctypes.POINTER(ctypes.c_int64), bp]
-        L.orc_fluxes.argtypes = [cp, dp, ctypes.c_int, dp, dp]
-        L.orc_prim2cons.argtypes = [cp, dp, dp]
-        L.orc_cons2prim.argtypes = [cp, dp, dp, bp]
-        L.orc_diag.argtypes = [cp, dp, dp, dp]
-        L.orc_diag_full.argtypes = [cp, dp, dp, dp, dp]
-        L.orc_grid_x1.argtypes = [cp, dp, dp]
-        L.orc_ppm_face.argtypes = [dp, dp, dp]
-        L.orc_geom.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
-        L.orc_point_state.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp] + [dp] * 10
-        L.orc_point_c2p.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int]
-        L.orc_point_floors.argtypes = [cp, ctypes.c_double, ctypes.c_double, dp]
-        L.orc_mc_slope.argtypes = [ctypes.c_double] * 3
-        L.orc_mc_slope.restype = ctypes.c_double
-        _lib = L
+        _lib = _load(LIB)
     return _lib
+
+
+def build_variant(source_text: str, out_dir: str, tag: str) -> str:
+    """Compile a modified copy of the oracle source (tests plant mistakes this way, to show that a
+    pin fails for them) with the oracle's own flags; returns the library path."""
+    src = os.path.join(out_dir, f"oracle_{tag}.c")
+    out = os.path.join(out_dir, f"liboracle_{tag}.so")
+    with open(src, "w") as fh:
+        fh.write(source_text)
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+                           "-o", out, src, "-lm"])
+    return out
+
+
+class using_library:
+    """Context manager: the module's functions call the oracle library at `path` inside the block."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.saved = lib()
+        _lib = _load(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 def _g(obj, name, default):
@@ -270,9 +307,19 @@ def fixups(cfg: OrcCfg, Pout, Pin, code):
     Pout = _arr(Pout, (8, cfg.n1, cfg.n2, cfg.n3))
     Pin = _arr(Pin, (8, cfg.n1, cfg.n2, cfg.n3))
     code = np.ascontiguousarray(code, dtype=np.int8).copy()
-    L = lib()
-    L.orc_fixups.restype = ctypes.c_int64
-    L.orc_fixups.argtypes = [ctypes.POINTER(OrcCfg), ctypes.POINTER(ctypes.c_double),
-                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int8)]
-    left = L.orc_fixups(ctypes.byref(cfg), _dp(Pout), _dp(Pin), _bp(code))
+    left = lib().orc_fixups(ctypes.byref(cfg), _dp(Pout), _dp(Pin), _bp(code))
     return Pout, code, int(left)
+
+
+def ghosts(cfg: OrcCfg, P):
+    """The interior state P[8][n1][n2][n3] with the boundary ghosts of Sec. 4.1 filled as a stage
+    fills them (polar interpolation first when the run sets it), returned with its ghost layers:
+    [8][n1 + 2 g1][n2 + 2 g2][n3 + 2 g3], g = 2 (PLM) or 3 (PPM) in every active direction."""
+    P = _arr(P, (8, cfg.n1, cfg.n2, cfg.n3))
+    g = 3 if cfg.recon == 1 else 2
+    shp = [n + (2 * g if n > 1 else 0) for n in (cfg.n1, cfg.n2, cfg.n3)]
+    out = np.zeros((8,) + tuple(shp))
+    rc = lib().orc_ghosts(ctypes.byref(cfg), _dp(P), _dp(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_ghosts failed ({rc})")
+    return out

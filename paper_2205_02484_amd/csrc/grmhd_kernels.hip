@@ -823,7 +823,8 @@ __global__ __launch_bounds__(256) void k_update_slow(const RunDev* __restrict__ 
 // fixups (Sec. 2.3): Jacobi rounds of neighbour averaging of the non-field primitives over the
 // failed cells of each run -- the 4-cross average when all four are valid, else the 4-diagonal
 // average, else the average of whichever of the 8 are valid; neighbours outside the interior do
-// not count.  Cells fixed in a round become valid in the next one.  One workgroup per run.
+// not count.  Cells fixed in a round become valid in the next one; a cell still failed after the
+// last round takes rho, u, u~ from the stage input and keeps its field.  One workgroup per run.
 // ------------------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_fixup(const RunDev* __restrict__ runs, int nruns, int stage) {
@@ -914,8 +915,9 @@ __global__ __launch_bounds__(256) void k_fixup(const RunDev* __restrict__ runs, 
             const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
             const int64_t ci = cell_index(R, i, j, k);
             if (R.code[ci] != -1) continue;
+            // the fluid variables fall back to the stage input; the field keeps its flux-CT update
 #pragma unroll
-            for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = Pin[q * vs + ci];
+            for (int q = 0; q < 5; ++q) Pout[q * vs + ci] = Pin[q * vs + ci];
             ++mine;
         }
         if (mine) {

@@ -332,14 +332,6 @@ class Batch:
     def advance(self, steps: int):
         _check(load().grmhd_batch_advance(self._h, int(steps)))
 
-    def diag_full(self):
-        """Horizon diagnostics (dict) and the radial profiles [6][n1]: Mdot, phi_B, Ldot, Edot,
-        ldot_in, ldot_out per radial cell."""
-        hz = Horizon()
-        rad = np.empty((6, self.grid.n1))
-        _check(load().grmhd_diag_full(self._h, ctypes.byref(hz), _ptr(rad)))
-        return ({k: getattr(hz, k) for k in ("mdot", "phi_b", "ldot", "edot", "phi_b_norm", "i_h")}, rad)
-
     def autotune(self, steps_per_candidate: int = 2) -> str:
         buf = ctypes.create_string_buffer(4096)
         _check(load().grmhd_batch_autotune(self._h, int(steps_per_candidate), buf, len(buf)))

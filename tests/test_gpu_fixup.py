@@ -65,11 +65,13 @@ def test_device_fixups_match_the_oracle(G, which, rounds):
     assert (left_g > 0) == (rounds == 2)
     assert np.isfinite(Pg).all()
     assert_parity(Pg, Po, 1e-14)
-    # untouched cells are untouched, unfixed cells carry the stage input
+    # untouched cells are untouched; unfixed cells carry the stage input's fluid variables and
+    # keep the stage output's (flux-CT) field
     ok = code >= 0
     assert np.array_equal(Pg[:, ok], Pout[:, ok])
     stuck = cg == -1
-    assert np.array_equal(Pg[:, stuck], Pin[:, stuck])
+    assert np.array_equal(Pg[0:5, stuck], Pin[0:5, stuck])
+    assert np.array_equal(Pg[5:8, stuck], Pout[5:8, stuck])
     assert (cg[code == -1] != -1).sum() > 0 and np.all(cg[code == -1] != 0)
 
 
@@ -83,3 +85,30 @@ def test_debug_fixup_rejects_bad_codes(G):
         ctx.debug_fixup(P, P, code)
     assert ei.value.code == G.EINVAL
     ctx.close()
+
+
+@pytest.mark.parametrize("rounds", [0, 2])
+def test_unfixed_cells_keep_the_corner_divergence(G, rounds):
+    """A divergence-free stage output with failed cells that no round (or not every round) can
+    fix: the device result equals the oracle's and the corner divergence stays at round-off."""
+    import math
+    from tests.test_oracle_unfixed import _case
+    from tests.test_oracle_step import _centre_gdet, corner_divb
+    cfg, P0, P1, Po, co, left = _case(rounds)
+    c = torus_2d_64()
+    code = np.zeros((c.n1, c.n2, 1), dtype=np.int8)
+    code[36, 33, 0] = -1
+    code[46:49, 30:33, 0] = -1
+    code[38:45, 28:35, 0] = -1
+    Pout = P1.copy()
+    Pout[0:5, code == -1] = np.nan
+    ctx = G.Context(c, P0, fixup_max_rounds=rounds)
+    Pg, cg, left_g = ctx.debug_fixup(Pout, P0, code)
+    ctx.close()
+    assert left_g == left > 0
+    assert np.array_equal(cg, co)
+    assert_parity(Pg, Po, 1e-14)
+    gd = _centre_gdet(cfg)
+    dx = [(math.log(cfg.r_out) - math.log(cfg.r_in)) / cfg.n1, 1 / cfg.n2]
+    div = corner_divb(Pg, gd[..., None], dx, 2)
+    assert np.abs(div).max() < 1e-13 * np.abs(P1[5:7] * gd[None, ..., None]).max() / min(dx)

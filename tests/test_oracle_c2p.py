@@ -228,8 +228,8 @@ def test_block_of_failures_is_filled_by_jacobi_rounds():
     assert np.allclose(P[:5, 5, 5, 0], ref, rtol=1e-15)
 
 
-def test_unfixable_cells_keep_the_stage_input():
+def test_unfixable_cells_keep_the_stage_input_fluid_and_their_field():
     bad = [(i, j) for i in range(12) for j in range(12)]
     cfg, Pout, Pin, code = _fixup_case(bad)
     P, _, left = orc.fixups(cfg, Pout, Pin, code)
-    assert left == 144 and np.array_equal(P, Pin)
+    assert left == 144 and np.array_equal(P[:5], Pin[:5]) and np.array_equal(P[5:], Pout[5:])
