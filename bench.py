@@ -2,9 +2,12 @@
 
 A zone-update is one interior cell advanced one full RK2 step (both stages: ghosts, face fluxes,
 CFL step, flux-CT, update with source, inversion, floors, fixups).  Inputs are the seeded
-synthetic torus, resident in HBM before the timed region; W untimed warm-up steps, then exactly K
-timed steps bracketed by device synchronisation, timed with HIP events on the run's stream (which
-also bracket every kernel, for the roofline figure of the dominant kernel).  Prints one JSON line.
+synthetic torus, resident in HBM before the timed region.  The launch-shape autotuner first runs
+its candidates on ordinary steps, then W untimed warm-up steps, then exactly K timed steps
+replayed from the captured HIP graph (no per-kernel events), bracketed by device synchronisation
+and timed with HIP events on the run's stream.  A separate pass of min(K, 20) steps with an event
+pair around every kernel gives the per-kernel split and the dominant kernel's duration for its
+roofline figure.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -18,18 +21,42 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic HBM bytes per unit processed by each kernel (state/flux traffic, FP64)
-#   flux_d : per face, the primitives of one cell (8 x 8 B) + the 7 stored flux slots written (56 B)
-#   update : per cell, its three lower faces' 7 flux slots (3 x 56 B), the stage input (64 B), P^n
-#            in stage 2 only (64 B; stage 1 shares the stage input), P_out (64 B), method code (1 B):
-#            297 B in stage 1, 361 B in stage 2, 329 B per launch on average
-#   bound  : per ghost cell, 8 primitives read and written
-ALG_BYTES = {"flux1": 120.0, "flux2": 120.0, "flux3": 120.0, "update": 329.0, "bound": 128.0}
+# Algorithmic HBM bytes of the method (the state alone, FP64, P-only state): stage 1 reads P^n and
+# writes P^{n+1/2} (128 B per cell); stage 2 reads P^{n+1/2} and P^n and writes P^{n+1} (192 B).
+# 320 B per zone-update; the update kernel is the one launch per stage that must move them.
+ALG_BYTES_STAGE = (128.0, 192.0)
+ALG_BYTES_ZU = sum(ALG_BYTES_STAGE)
+# Intermediate traffic of this implementation's face kernels (context, not algorithmic): per face
+# the 8 primitives of one cell read once per direction and the 7 stored flux slots written.
+FACE_BYTES = 120.0
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 # committed rocprofv3 counters of the 256^3 workload, per face reconstruction
 COUNTERS = {"plm": os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256.json"),
             "ppm": os.path.join(ROOT, "profiles", "hbm_counters_torus3d_256_ppm.json")}
+# FP64 operations per zone-update of the method, counted on an op-counting build of the oracle
+# (every add/sub/mul/div/sqrt/pow of one RK2 step on the benchmark torus's physics)
+FLOP_COUNT = os.path.join(ROOT, "profiles", "oracle_flop_count.json")
+FLOP_KEY = "torus3d_256x256x256_physics_at_64cubed"
+
+
+def oracle_flops_per_zu():
+    try:
+        with open(FLOP_COUNT) as fh:
+            return float(json.load(fh)["per_zone_update"][FLOP_KEY]["total"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def kernel_source_hash():
@@ -82,6 +109,7 @@ def cpu_baseline(cfg, P, nsteps):
     el = time.perf_counter() - t0
     zones = cfg.n1 * cfg.n2 * cfg.n3
     return {"value": zones * nsteps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{nsteps} RK2 steps of the full {cfg.n1}x{cfg.n2}x{cfg.n3} torus, OpenMP over cells, "
                       f"{el:.1f} s wall"}
 
@@ -94,7 +122,7 @@ def ensemble_legs(args, stream):
     from paper_2205_02484_amd.torus_init import make_torus
     inputs = [make_torus(j.cfg) for j in jobs]
     print(f"[bench] ensemble: {len(jobs)} tori x {args.ensemble_steps} steps, batched", file=sys.stderr, flush=True)
-    bat = serve.run_batched(jobs, steps_per_launch=25, stream=stream, inputs=inputs)
+    bat = serve.run_batched(jobs, steps_per_launch=25, stream=stream, inputs=inputs, autotune_steps=1)
     print(f"[bench] ensemble batched {bat['zu_per_s']:.3e} ZU/s; sequential", file=sys.stderr, flush=True)
     seq = serve.run_sequential(jobs, stream=stream, inputs=inputs)
     print(f"[bench] ensemble sequential {seq['zu_per_s']:.3e} ZU/s", file=sys.stderr, flush=True)
@@ -113,6 +141,7 @@ def ensemble_legs(args, stream):
         "batched_zu_per_s": bat["zu_per_s"], "batched_seconds": bat["seconds"],
         "sequential_zu_per_s": seq["zu_per_s"], "sequential_seconds": seq["seconds"],
         "batched_over_sequential": bat["zu_per_s"] / seq["zu_per_s"],
+        "batched_autotune": bat["autotune"],
         "served": {"duration_s": args.serve_seconds, "rate_hz": rate, "load": 0.8, "jobs": srv["jobs"],
                    "p50_s": srv["p50_s"], "p99_s": srv["p99_s"], "mean_s": srv["mean_s"],
                    "zu_per_s": srv["zu_per_s"], "seconds": srv["seconds"],
@@ -125,6 +154,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--autotune-steps", type=int, default=2,
+                    help="ordinary steps per candidate launch shape of the autotuner, before the warm-up")
     ap.add_argument("--workload", default="torus3d_256x256x256")
     ap.add_argument("--recon", choices=("plm", "ppm"), default="plm",
                     help="face reconstruction: PLM with the MC limiter (the paper's) or PPM")
@@ -169,45 +200,57 @@ def main():
     stream = torch.cuda.Stream()
     ctx = grmhd.Context(cfg, P, stream=stream)
     print(f"[bench] {args.workload}: {zones} zones, warmup {args.warmup}", file=sys.stderr, flush=True)
-    # the launch-shape autotuner runs inside the warm-up (5 candidate shapes x 2 ordinary steps)
-    tuned = None
-    warm = args.warmup
-    if warm >= 10:
-        tuned = ctx.autotune(2)
-        warm -= 10
-    ctx.steps(warm)
+    # the launch-shape autotuner runs its candidates on ordinary steps before the warm-up (its
+    # steps advance the run like any other and are not timed)
+    tuned = ctx.autotune(args.autotune_steps) if args.autotune_steps > 0 else ""
+    ctx.steps(args.warmup)
     torch.cuda.synchronize()
-    ctx.kernel_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record(stream)
-    ctx.steps(args.steps)
+    ctx.steps(args.steps)                  # graph replays: the product path, no per-kernel events
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    kt = ctx.kernel_times()
     t, nstep, nfail = ctx.get_time()
-    ctx.kernel_timing(False)
     ms_per_step = ms / args.steps
     value = zones * args.steps / (ms * 1e-3)
     print(f"[bench] {ms_per_step:.3f} ms/step, {value:.3e} ZU/s, t={t:.4f}, failures={nfail}",
           file=sys.stderr, flush=True)
+    # per-kernel split: a separate pass with an event pair around every kernel (plain launches)
+    nsplit = min(args.steps, 20)
+    ctx.kernel_timing(True)
+    ctx.steps(nsplit)
+    kt = ctx.kernel_times()
+    ctx.kernel_timing(False)
+    torch.cuda.synchronize()
+    split_ms = sum(v[0] * v[1] for v in kt.values()) / max(nsplit, 1)
 
-    # dominant kernel by total time in the timed region
+    # dominant kernel: the update (flux-CT, update with source, inversion, floors), which is the
+    # launch per stage that must move the method's state bytes
     tot = {k: v[0] * v[1] for k, v in kt.items()}
-    dom = max((k for k in tot if k in ALG_BYTES), key=lambda k: tot[k])
+    dom = "update"
     avg_ms = kt[dom][0]
-    units = units_per_launch(dom, n1, n2, n3, args.recon)
-    achieved = ALG_BYTES[dom] * units / (avg_ms * 1e-3) / 1e9
+    alg_launch = 0.5 * (ALG_BYTES_STAGE[0] + ALG_BYTES_STAGE[1]) * zones   # both stages' launches averaged
+    achieved = alg_launch / (avg_ms * 1e-3) / 1e9
     prof = profiled_counters(args.workload, args.recon)
     traffic = None
     if prof and dom in prof:
         traffic = prof[dom]["hbm_read_bytes"] + prof[dom]["hbm_write_bytes"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                "avg_ms": avg_ms, "alg_bytes_per_unit": ALG_BYTES[dom], "units_per_launch": units,
-                "alg_bytes_per_launch": ALG_BYTES[dom] * units}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom, "avg_ms": avg_ms,
+                "alg_bytes_per_unit": list(ALG_BYTES_STAGE), "unit_name": "cell (stage 1, stage 2)",
+                "units_per_launch": zones, "alg_bytes_per_launch": alg_launch}
+    # whole step against the method's own bytes and FP64 operations
+    flops_zu = oracle_flops_per_zu()
+    t_bytes = ALG_BYTES_ZU * zones / (HBM_PEAK_GBS * 1e9) * 1e3
+    t_flops = flops_zu * zones / (FP64_PEAK_TFLOPS * 1e12) * 1e3 if flops_zu else None
+    t_roof = max(t_bytes, t_flops or 0.0)
+    step_roof = {"alg_bytes_per_zu": ALG_BYTES_ZU, "alg_fp64_ops_per_zu": flops_zu,
+                 "t_bytes_ms": t_bytes, "t_fp64_ms": t_flops, "t_roofline_ms": t_roof,
+                 "bound": "fp64" if (t_flops or 0.0) > t_bytes else "hbm",
+                 "frac": t_roof / ms_per_step,
+                 "hbm_frac_alg_bytes": ALG_BYTES_ZU * zones / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)}
     if prof:
         # measured HBM and FP64 rates of every stage kernel at the live durations (context)
         roofline["per_kernel_measured"] = {
@@ -215,6 +258,10 @@ def main():
                 "fp64_TFLOPs": v["fp64_flop"] / (kt[k][0] * 1e-3) / 1e12,
                 "fp64_frac": v["fp64_flop"] / (kt[k][0] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
             for k, v in prof.items() if k in kt and kt[k][0] > 0}
+        per_step = sum((v["hbm_read_bytes"] + v["hbm_write_bytes"]) * kt[k][1] / max(nsplit, 1)
+                       for k, v in prof.items() if k in kt)
+        step_roof["traffic_per_step"] = per_step
+        step_roof["traffic_over_alg"] = per_step / (ALG_BYTES_ZU * zones)
     kernels = {k: {"avg_ms": v[0], "launches": v[1], "share": tot[k] / max(sum(tot.values()), 1e-30)}
                for k, v in kt.items()}
 
@@ -235,8 +282,11 @@ def main():
                    "gamma": cfg.gam, "r_out": cfg.r_out, "r_in_torus": cfg.r_in, "r_max": cfg.r_max,
                    "cfl": cfg.cfl, "riemann": "llf", "recon": args.recon},
         "roofline": roofline,
+        "step_roofline": step_roof,
         "kernels": kernels,
-        "autotune": [ln for ln in (tuned or "").splitlines() if ln.startswith("chosen")],
+        "kernel_split": {"steps": nsplit, "ms_per_step_with_events": split_ms},
+        "autotune": {"steps": 5 * args.autotune_steps,
+                     "chosen": [ln for ln in (tuned or "").splitlines() if ln.startswith("chosen")]},
         "sim_time": t,
         "unfixed_cells": nfail,
     }

@@ -127,8 +127,10 @@ def run_sequential(jobs: List[Job], stream=None, inputs: Optional[List[np.ndarra
 
 def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
                 keep: Optional[Callable[[Job, np.ndarray], None]] = None,
-                inputs: Optional[List[np.ndarray]] = None) -> Dict[str, float]:
-    """All jobs resident together, advanced in one kernel chain until each is done."""
+                inputs: Optional[List[np.ndarray]] = None, autotune_steps: int = 0) -> Dict[str, float]:
+    """All jobs resident together, advanced in one kernel chain until each is done.  With
+    autotune_steps > 0 the launch-shape autotuner first runs that many ordinary steps per candidate
+    shape on the whole ensemble (they count towards each job's steps and are timed with the rest)."""
     b = grmhd.Batch(stream=stream)
     if inputs is None:
         inputs = [make_torus(j.cfg) for j in jobs]
@@ -142,6 +144,7 @@ def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
         by_handle[h] = j
     left = len(jobs)
     zu = 0
+    tuned = b.autotune(autotune_steps) if autotune_steps > 0 else ""
     while left:
         b.advance(steps_per_launch)
         for h in b.poll():
@@ -153,7 +156,8 @@ def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
             left -= 1
     el = time.perf_counter() - t0
     b.close()
-    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el}
+    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el,
+            "autotune": [ln for ln in tuned.splitlines() if ln.startswith("chosen")]}
 
 
 def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, stream=None,

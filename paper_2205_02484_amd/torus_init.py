@@ -61,6 +61,14 @@ class TorusConfig:
     n_x: int = 4                   # power of the hyper-exponential term
     recon: str = "plm"             # face reconstruction: "plm" (MC limiter) or "ppm"
     pole_fix: int = 0              # cells next to each pole whose u~2 is interpolated to 0 (paper: 2)
+    # optional structure of a magnetised funnel (off by default; checks of the magnetisation
+    # ceilings and the Lorentz cap): a vertical field of this amplitude threading the whole grid,
+    # atmosphere included (A_phi = b_vert r^2 sin^2(theta) / 2, added after the loop's beta
+    # normalisation), and a radial outflow of Lorentz factor jet_lorentz in the jet_cells rows next
+    # to each pole beyond twice the horizon radius
+    b_vert: float = 0.0
+    jet_lorentz: float = 0.0
+    jet_cells: int = 4
 
     @property
     def r_horizon(self) -> float:
@@ -301,7 +309,20 @@ def make_torus(cfg: TorusConfig) -> np.ndarray:
         B1 = B1 * scale
         B2 = B2 * scale
 
-    # floors (the atmosphere starts at the floor values with u~ = 0)
+    if cfg.b_vert != 0.0:
+        ie, je = np.meshgrid(np.arange(n1 + 1) - 0.5, np.arange(n2 + 1) - 0.5, indexing="ij")
+        rc_, thc_, _ = mks_centres(cfg, ie, je)
+        av = 0.5 * cfg.b_vert * rc_ * rc_ * np.sin(thc_) ** 2
+        x1lo, x1hi = x1_range(cfg)
+        dx1 = (x1hi - x1lo) / n1
+        dx2 = 1.0 / n2
+        B1 = B1 + (av[:-1, 1:] + av[1:, 1:] - av[:-1, :-1] - av[1:, :-1]) / (2.0 * dx2 * gdet)
+        B2 = B2 - (av[1:, :-1] + av[1:, 1:] - av[:-1, :-1] - av[:-1, 1:]) / (2.0 * dx1 * gdet)
+    if cfg.jet_lorentz > 1.0:
+        jet = (r > 2.0 * cfg.r_horizon) & ((jj < cfg.jet_cells) | (jj >= n2 - cfg.jet_cells)) & ~inside
+        ut1 = np.where(jet, math.sqrt(cfg.jet_lorentz ** 2 - 1.0) / np.sqrt(g["11"]), ut1)
+
+    # floors (the atmosphere starts at the floor values with u~ = 0 outside a jet)
     r3 = np.broadcast_to(r[:, :, None], shape)
     rho_fl = np.maximum(cfg.fl_abs, cfg.rho_fl_coef * r3 ** cfg.rho_fl_pow)
     u_fl = np.maximum(cfg.fl_abs, cfg.u_fl_coef * r3 ** cfg.u_fl_pow)

@@ -63,3 +63,17 @@ def test_unit_counts_per_launch():
     for recon, g in (("plm", 2), ("ppm", 3)):
         ghosts = ((n1 + 2 * g) * (n2 + 2 * g) - n1 * n2) * n3
         assert bench.units_per_launch("bound", n1, n2, n3, recon) == ghosts
+
+
+def test_step_roofline_inputs():
+    """320 B per zone-update (stage 1 reads and writes the state, stage 2 also reads P^n) and the
+    FP64 operation count of the committed op-counting oracle run, which must cover the benchmark
+    torus's physics."""
+    assert bench.ALG_BYTES_STAGE == (128.0, 192.0) and bench.ALG_BYTES_ZU == 320.0
+    f = bench.oracle_flops_per_zu()
+    assert f is not None and 3e3 < f < 2e4
+    with open(bench.FLOP_COUNT) as fh:
+        js = json.load(fh)
+    d = js["per_zone_update"][bench.FLOP_KEY]
+    assert d["total"] == sum(d[k] for k in ("add", "mul", "div", "sqrt", "pow", "other_libm"))
+    assert "command" in js

@@ -81,6 +81,32 @@ def test_ensemble_jobs_equal_solo_runs_and_the_oracle(G):
         assert max_rel_err(Ps, Po) < 1e-9
 
 
+def test_ensemble_sample_matches_the_oracle(G):
+    """The 48-torus ensemble of the benchmark advanced together for ten steps; a seeded sample of
+    its members (2D and 3D) against the oracle run alone on each."""
+    from paper_2205_02484_amd import serve
+    jobs = serve.ensemble_jobs(seed=4, nsteps=10)
+    rng = np.random.default_rng(7)
+    pick = sorted(set(rng.choice(24, 2, replace=False).tolist()) | set((24 + rng.choice(24, 2, replace=False)).tolist()))
+    b = G.Batch()
+    ids = {j.jid: b.admit(j.cfg, make_torus(j.cfg), j.nsteps) for j in jobs}
+    done = set()
+    for _ in range(10):
+        b.advance(5)
+        done |= set(b.poll())
+        if len(done) == len(ids):
+            break
+    assert done == set(ids.values())
+    for x in pick:
+        c = jobs[x].cfg
+        print("member", x, c.n1, c.n2, c.n3, flush=True)
+        Pb, tb, nb = b.fetch(ids[x])
+        Po, dto, nfo, _ = orc.step(orc.make_cfg(c), make_torus(c), 10)
+        assert nb == 10 and tb == pytest.approx(dto.sum(), rel=1e-10)
+        assert max_rel_err(Pb, Po) < 1e-8, x
+    b.close()
+
+
 def test_continuous_admission_midway_keeps_results(G):
     """A job admitted while another is part-way through does not change either result."""
     c0, c1 = _cfgs()[0], _cfgs()[3]

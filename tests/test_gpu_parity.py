@@ -216,6 +216,44 @@ def test_one_step_256cubed_torus_in_bench_configuration(G):
     assert_parity(Pg, Po, 1e-12)
 
 
+def _run_graph(G, c, P, nsteps, **over):
+    """The benchmark's path: CFL steps enqueued as graph replays (grmhd_steps)."""
+    cfg = orc.make_cfg(c, **over)
+    Po, dto, nfo, codeo = orc.step(cfg, P, nsteps)
+    ctx = G.Context(c, P, **over)
+    ctx.steps(nsteps)
+    Pg, codeg = ctx.get_prims(), ctx.get_codes()
+    t, ns, nf = ctx.get_time()
+    ctx.close()
+    assert ns == nsteps and nf == nfo
+    assert t == pytest.approx(dto.sum(), rel=1e-10)
+    return Pg, Po, codeg, codeo
+
+
+@pytest.mark.parametrize("recon", ["plm", "ppm"])
+@pytest.mark.parametrize("shape", [(24, 16, 64), (20, 12, 128)])
+def test_ten_steps_on_the_uniform_metric_path(G, recon, shape):
+    """n3 a multiple of 64: the instantiation the 256^3 benchmark runs (scalar metric loads,
+    X1-face rows i-fastest, update workgroups on consecutive j), ten graph-replayed CFL steps."""
+    c = _small3d(n1=shape[0], n2=shape[1], n3=shape[2], seed=31, recon=recon)
+    P = make_torus(c)
+    print("case", recon, shape, flush=True)
+    Pg, Po, cg, co = _run_graph(G, c, P, 1)
+    assert np.array_equal(cg, co)
+    assert_parity(Pg, Po, 1e-12)
+    Pg, Po, cg, co = _run_graph(G, c, P, 10)
+    assert np.array_equal(cg, co)
+    assert_parity(Pg, Po, 1e-8)
+
+
+def test_ten_steps_128x64x64_torus_graph_path(G):
+    c = torus_128x64x64()
+    P = make_torus(c)
+    Pg, Po, cg, co = _run_graph(G, c, P, 10)
+    assert np.array_equal(cg, co)
+    assert_parity(Pg, Po, 1e-8)
+
+
 def _hyperexp(n=(96, 64, 1), **kw):
     """The paper's production radial grid (Sec. 4.1): hyper-exponential beyond r = 400, n_X = 4,
     outer edge 5000 M."""
