@@ -43,21 +43,24 @@ enum {
     KB_BOUND = 0,
     KB_F1, KB_F2, KB_F3, KB_F1N, KB_F2N, KB_F3N,
     KB_P1, KB_P2, KB_P3, KB_P1N, KB_P2N, KB_P3N,
-    KB_UPD, KB_UPDN, NK
+    KB_UPD, KB_UPDN, KB_EMF, NK
 };
 // flux table of direction d for runs with (uni, ppm)
 constexpr int flux_kind(int d, bool uni, bool ppm) { return KB_F1 + (d - 1) + (uni ? 0 : 3) + (ppm ? 6 : 0); }
 
-// Launch shape of one stage-kernel kind: threads per workgroup and block order (bit 0 set:
-// XCD-contiguous).  The autotuner picks one per kind.
+// Launch shape of one stage-kernel kind: threads per workgroup, block order (bit 0 set:
+// XCD-contiguous) and, for the marching X1/X2 face kernels, faces per wave segment.  The
+// autotuner picks one per kind.
 struct Shape {
     int bs = 256;
     int sched = 1;
+    int seg = 16;
 };
-const Shape kCandidates[] = {{256, 1}, {128, 1}, {64, 1}, {256, 0}, {128, 0}};
+const Shape kCandidates[] = {{256, 1, 16}, {128, 1, 16}, {64, 1, 16}, {256, 0, 16}, {128, 0, 16},
+                             {128, 1, 8}, {256, 1, 32}, {128, 1, 64}};
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 // kernel kinds reported by grmhd_kernel_times
-enum { TK_BOUND = 0, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_DT, TK_UPDATE, TK_FIXUP, TK_SLOW, NTK };
+enum { TK_BOUND = 0, TK_FLUX1, TK_FLUX2, TK_FLUX3, TK_DT, TK_UPDATE, TK_FIXUP, TK_SLOW, TK_EMF, NTK };
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
@@ -385,7 +388,7 @@ struct Engine {
         use_graph = !(ng && ng[0] == '1');
         return GRMHD_OK;
     }
-    static int64_t elems(const RunDev& R, int kind, int bs) {
+    static int64_t elems(const RunDev& R, int kind, int bs, int seg) {
         const int64_t n1 = R.n1, n2 = R.n2, n3 = R.n3;
         switch (kind) {
             case KB_BOUND: {
@@ -397,6 +400,9 @@ struct Engine {
                 const int x = kind - KB_F1, d = x % 3 + 1;
                 const bool uni = (x / 3) % 2 == 0, ppm = x >= 6;
                 if (uni != (bool)R.geo_uniform || ppm != (bool)R.ppm) return 0;
+                // marching X1/X2 kernels: one wave per segment of seg faces, 64 k and a row
+                if (uni && !ppm && d == 1) return R.act1 ? march_waves(R, 1, seg) * 64 : 0;
+                if (uni && !ppm && d == 2) return R.act2 ? march_waves(R, 2, seg) * 64 : 0;
                 if (d == 1) return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
                 if (d == 2) return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
                 return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3 : 0;
@@ -404,6 +410,8 @@ struct Engine {
             // uniform-metric update: workgroups of bs/64 waves on consecutive j (n2 padded to a
             // multiple of that)
             case KB_UPD: return R.geo_uniform ? n1 * ((n2 + bs / 64 - 1) / (bs / 64) * (bs / 64)) * n3 : 0;
+            // edge EMFs: runs with at least two active directions
+            case KB_EMF: return (R.act1 + R.act2 + R.act3 >= 2) ? (n1 + 1) * (n2 + 1) * n3 : 0;
             default: return R.geo_uniform ? 0 : n1 * n2 * n3;
         }
     }
@@ -425,7 +433,7 @@ struct Engine {
             int acc = 0;
             for (int r = 0; r < n; ++r) {
                 boff[kind * (cap + 1) + r] = acc;
-                const int64_t ne = elems(runs[r]->h, kind, shape[kind].bs);
+                const int64_t ne = elems(runs[r]->h, kind, shape[kind].bs, shape[kind].seg);
                 acc += (int)((ne + shape[kind].bs - 1) / shape[kind].bs);
             }
             boff[kind * (cap + 1) + n] = acc;
@@ -481,7 +489,7 @@ struct Engine {
                     const bool uni = v & 1, ppm = v >> 1;
                     const int k = flux_kind(d, uni, ppm);
                     launch_flux(d, d_runs, boff(k), n, nblk[k], which, stage == 1, 0, uni, ppm, shape[k].bs,
-                                shape[k].sched, st);
+                                shape[k].sched, shape[k].seg, st);
                 }
                 mark(TK_FLUX1 + d - 1);
             }
@@ -490,6 +498,9 @@ struct Engine {
                 launch_dt(d_runs, n, st);
                 mark(TK_DT);
             }
+            mark(TK_EMF);
+            launch_emf(d_runs, boff(KB_EMF), n, nblk[KB_EMF], shape[KB_EMF].bs, shape[KB_EMF].sched, st);
+            mark(TK_EMF);
             mark(TK_UPDATE);
             launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, 1, shape[KB_UPD].bs, shape[KB_UPD].sched, st);
             launch_update(d_runs, boff(KB_UPDN), n, nblk[KB_UPDN], stage, 0, shape[KB_UPDN].bs, shape[KB_UPDN].sched,
@@ -512,12 +523,14 @@ struct Engine {
         if (runs.empty() || reps <= 0) return GRMHD_OK;
         int tk_of[NK];
         for (int k = 0; k < NK; ++k)
-            tk_of[k] = k == KB_BOUND ? TK_BOUND : (k >= KB_UPD ? TK_UPDATE : TK_FLUX1 + (k - KB_F1) % 3);
+            tk_of[k] = k == KB_BOUND ? TK_BOUND
+                       : (k == KB_EMF ? TK_EMF : (k >= KB_UPD ? TK_UPDATE : TK_FLUX1 + (k - KB_F1) % 3));
         double best_ms[NK];
         int best[NK];
         for (int k = 0; k < NK; ++k) { best_ms[k] = 1e300; best[k] = 0; }
         const bool was_timing = timing;
         char line[256];
+        std::string detail;
         for (int c = 0; c < kNumCandidates; ++c) {
             for (int k = 0; k < NK; ++k) shape[k] = kCandidates[c];
             dirty = true;
@@ -533,11 +546,9 @@ struct Engine {
                 const int tk = tk_of[k];
                 if (!t_n[tk]) continue;
                 const double ms = t_ms[tk] / (double)t_n[tk];
-                if (report) {
-                    snprintf(line, sizeof(line), "kind %d bs %d sched %d: %.4f ms\n", k, kCandidates[c].bs,
-                             kCandidates[c].sched, ms);
-                    *report += line;
-                }
+                snprintf(line, sizeof(line), "kind %d bs %d sched %d seg %d: %.4f ms\n", k, kCandidates[c].bs,
+                         kCandidates[c].sched, kCandidates[c].seg, ms);
+                detail += line;
                 if (ms < best_ms[k]) { best_ms[k] = ms; best[k] = c; }
             }
         }
@@ -545,10 +556,13 @@ struct Engine {
         for (int k = 0; k < NTK; ++k) { t_ms[k] = 0.0; t_n[k] = 0; }
         dirty = true;
         if (report) {
+            // the choice first, so that a short caller buffer still holds it
             for (int k = 0; k < NK; ++k) {
-                snprintf(line, sizeof(line), "chosen kind %d: bs %d sched %d\n", k, shape[k].bs, shape[k].sched);
+                snprintf(line, sizeof(line), "chosen kind %d: bs %d sched %d seg %d\n", k, shape[k].bs, shape[k].sched,
+                         shape[k].seg);
                 *report += line;
             }
+            *report += detail;
         }
         return GRMHD_OK;
     }
@@ -942,8 +956,11 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     const int kind = flux_kind(d, R.geo_uniform, R.ppm);
     HIPCHK(hipMemsetAsync(R.var->cmax, 0, sizeof(R.var->cmax), st));
     launch_bound(E.d_runs, E.boff(KB_BOUND), 1, E.nblk[KB_BOUND], 0, E.shape[KB_BOUND].bs, E.shape[KB_BOUND].sched, st);
-    launch_flux(d, E.d_runs, E.boff(kind), 1, E.nblk[kind], 0, 1, 1, 0, R.ppm, E.shape[kind].bs, E.shape[kind].sched,
-                st);
+    // one thread per face of the direction (the stage chain's table may count marching waves)
+    const int64_t nface = (int64_t)(d == 1 ? R.n1 + 1 : R.n1 + 2 * R.act1) * (d == 2 ? R.n2 + 1 : R.n2 + 2 * R.act2) * R.n3;
+    const int fbs = E.shape[kind].bs;
+    launch_flux(d, E.d_runs, E.boff(kind), 1, (int)((nface + fbs - 1) / fbs), 0, 1, 1, 0, R.ppm, fbs,
+                E.shape[kind].sched, E.shape[kind].seg, st);
     const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
     double* dF = nullptr;
     HIPCHK(hipMalloc(&dF, n * 8));

@@ -106,6 +106,16 @@ __device__ __forceinline__ void gst(double* base, uint32_t e, double v) {
     *(g_double*)((g_char*)base + e * 8u) = v;
 }
 
+// Wave-uniform read of a table no stage kernel writes (the metric) through the constant address
+// space: the load is a scalar load even after vector stores of the same kernel, which a
+// global-space load in a loop with stores is not (the compiler cannot rule out a clobber).
+typedef __attribute__((address_space(4))) const char k_char;
+typedef __attribute__((address_space(4))) const double k_double;
+
+__device__ __forceinline__ double kld(const double* base, uint32_t e) {
+    return *(const k_double*)((const k_char*)base + e * 8u);
+}
+
 __device__ __forceinline__ int64_t cell_index(const RunDev& R, int i, int j, int k) {
     return (int64_t)(i + NG) * R.s1 + (int64_t)(j + NG) * R.s2 + k;
 }
@@ -137,6 +147,26 @@ __device__ __forceinline__ void load_geo(const double* __restrict__ g, int64_t n
     G.gdet = gld(g + G_DET * np, gi);
     G.alpha = gld(g + G_ALPHA * np, gi);
     G.ialpha = gld(g + G_IALPHA * np, gi);
+}
+
+// load_geo for a wave-uniform point gi, as scalar loads
+__device__ __forceinline__ void load_geo_k(const double* __restrict__ g, int64_t np, uint32_t gi, Geo& G) {
+    G.gtt = kld(g + G_TT * np, gi);
+    G.gt1 = kld(g + G_T1 * np, gi);
+    G.gt3 = kld(g + G_T3 * np, gi);
+    G.g11 = kld(g + G_11 * np, gi);
+    G.g13 = kld(g + G_13 * np, gi);
+    G.g22 = kld(g + G_22 * np, gi);
+    G.g33 = kld(g + G_33 * np, gi);
+    G.Gtt = kld(g + GI_TT * np, gi);
+    G.Gt1 = kld(g + GI_T1 * np, gi);
+    G.G11 = kld(g + GI_11 * np, gi);
+    G.G13 = kld(g + GI_13 * np, gi);
+    G.G22 = kld(g + GI_22 * np, gi);
+    G.G33 = kld(g + GI_33 * np, gi);
+    G.gdet = kld(g + G_DET * np, gi);
+    G.alpha = kld(g + G_ALPHA * np, gi);
+    G.ialpha = kld(g + G_IALPHA * np, gi);
 }
 
 // sqrt(x) and 1/sqrt(x) together, for normal x > 0: the hardware reciprocal-square-root estimate

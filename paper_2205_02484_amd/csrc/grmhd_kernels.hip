@@ -254,12 +254,55 @@ __device__ __forceinline__ constexpr int flux_store_slot(int q) {
     return q == NCS - 1 ? FS_ENT : (q == 4 + D ? FS_BN : flux_slot<D>(q));
 }
 
-// One face: returns c_w (0 when the face does not count for the CFL step).  The left state's
-// conserved vector, flux and speeds are finished before the right state is formed, which keeps
-// the live register set to one state plus two flux vectors.  With ENT = false the entropy
-// component (read only by the entropy inversion of the slow path, which recomputes it for its
-// own faces) is neither computed nor stored: that saves both powers of rho per face.  PPM reads
-// three cells on each side of the face (PLM two), which the run's ghost layers cover.
+// Riemann flux through one face from its two reconstructed states (Sec. 2.2): the state, conserved
+// vector, flux and simplified-dispersion speeds of each side, then LLF (or HLL) into out[q] for
+// the NQ components the caller keeps; returns c_w.  The left side is finished before the right
+// state is formed, which keeps the live register set to one state plus two flux vectors.  With
+// ENT = false the entropy component (read only by the entropy inversion of the slow path, which
+// recomputes it for its own faces) is neither computed nor combined: that saves both powers of rho.
+template <int D, bool ENT>
+__device__ __forceinline__ double riemann_face(const RunDev& R, const double* Pl, const double* Pr, const Geo& G,
+                                               double* out) {
+    constexpr int NQ = ENT ? NCS : 8;
+    const double gam = R.gam;
+    double Ul[NCS], Fl[NCS];
+    double c1l, c2l;
+    {
+        St s;
+        prim_state(Pl, G, gam, s);
+        const double ent = ENT ? s.p * pow(Pl[0], 1.0 - gam) : 0.0;
+        wave_speeds<D>(s, G, gam, c1l, c2l);
+        flux_of<0>(Pl, s, G, ent, Ul);
+        flux_of<D>(Pl, s, G, ent, Fl);
+    }
+    St s;
+    prim_state(Pr, G, gam, s);
+    const double entr = ENT ? s.p * pow(Pr[0], 1.0 - gam) : 0.0;
+    double c1r, c2r;
+    wave_speeds<D>(s, G, gam, c1r, c2r);
+    const double cmax = fmax(0.0, fmax(c1r, c1l));
+    const double cmin = fmax(0.0, fmax(-c2r, -c2l));
+    const double cwf = fmax(cmax, cmin);
+    double Ur[NCS], Fr[NCS];
+    flux_of<0>(Pr, s, G, entr, Ur);
+    flux_of<D>(Pr, s, G, entr, Fr);
+    if (R.riemann == 1) {
+        const double den = cmax + cmin;
+        const double id = den > 0.0 ? 1.0 / den : 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            out[q] = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
+                               : 0.5 * (Fl[q] + Fr[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
+    }
+    return cwf;
+}
+
+// One face: reconstruction from the cells on either side, then riemann_face; returns c_w (0 when
+// the face does not count for the CFL step).  PPM reads three cells on each side of the face (PLM
+// two), which the run's ghost layers cover.
 template <int D, bool UNI, bool ENT, bool PPM>
 __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k, int which, double* ent_out) {
     constexpr int NQ = ENT ? NCS : 8;
@@ -314,40 +357,8 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         }
     }
     if (!UNI) load_geo(D == 3 ? R.gc : R.gf[D], R.gpts, geo_index(R, i, j), G);
-    const double gam = R.gam;
-    double Ul[NCS], Fl[NCS];
-    double c1l, c2l;
-    {
-        St s;
-        prim_state(Pl, G, gam, s);
-        const double ent = ENT ? s.p * pow(Pl[0], 1.0 - gam) : 0.0;
-        wave_speeds<D>(s, G, gam, c1l, c2l);
-        flux_of<0>(Pl, s, G, ent, Ul);
-        flux_of<D>(Pl, s, G, ent, Fl);
-    }
-    St s;
-    prim_state(Pr, G, gam, s);
-    const double entr = ENT ? s.p * pow(Pr[0], 1.0 - gam) : 0.0;
-    double c1r, c2r;
-    wave_speeds<D>(s, G, gam, c1r, c2r);
-    const double cmax = fmax(0.0, fmax(c1r, c1l));
-    const double cmin = fmax(0.0, fmax(-c2r, -c2l));
-    const double cwf = fmax(cmax, cmin);
-    double Ur[NCS], Fr[NCS];
-    flux_of<0>(Pr, s, G, entr, Ur);
-    flux_of<D>(Pr, s, G, entr, Fr);
     double out[NCS];
-    if (R.riemann == 1) {
-        const double den = cmax + cmin;
-        const double id = den > 0.0 ? 1.0 / den : 0.0;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-            out[q] = den > 0.0 ? (cmax * Fl[q] + cmin * Fr[q] - cmax * cmin * (Ur[q] - Ul[q])) * id
-                               : 0.5 * (Fl[q] + Fr[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) out[q] = 0.5 * (Fl[q] + Fr[q] - cwf * (Ur[q] - Ul[q]));
-    }
+    const double cwf = riemann_face<D, ENT>(R, Pl, Pr, G, out);
     if (ent_out) {
         *ent_out = out[NCS - 1];
         return 0.0;
@@ -369,6 +380,25 @@ __device__ __forceinline__ double entropy_flux(const RunDev& R, int i, int j, in
     if (R.ppm) flux_face<D, false, true, true>(R, i, j, k, which, &f);
     else flux_face<D, false, true, false>(R, i, j, k, which, &f);
     return f;
+}
+
+// CFL bookkeeping of the face kernels: wave and workgroup maximum of c_w, then one atomic max per
+// workgroup on the run's slot for direction D (non-negative doubles order like their bit patterns).
+template <int D>
+__device__ __forceinline__ void cfl_max(const RunDev& R, double cw) {
+    __shared__ double red[4];
+    cw = wave_max(cw);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = cw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+        unsigned long long* slot = &R.var->cmax[D - 1];
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+        const unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bits > cur) atomicMax(slot, bits);
+    }
 }
 
 template <int D, bool ENT, bool UNI, bool PPM>
@@ -418,20 +448,164 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
         }
         cw = flux_face<D, UNI, ENT, PPM>(R, i, j, (int)k, which, nullptr);
     }
-    if (!do_cfl) return;
-    __shared__ double red[4];
-    cw = wave_max(cw);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) red[wid] = cw;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-        unsigned long long* slot = &R.var->cmax[D - 1];
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
-        const unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (bits > cur) atomicMax(slot, bits);
+    if (do_cfl) cfl_max<D>(R, cw);
+}
+
+// Face fluxes along D in {1, 2} for PLM runs with n3 % 64 == 0, marched along the face normal: a
+// wave holds 64 consecutive k of one transverse row and walks a segment of `seg` faces along D,
+// carrying the last two cells and the left state of its next face in registers, so each face
+// loads one new cell (8 values) where the one-face kernel loads four, and each cell's MC slope is
+// formed once instead of twice.  The arithmetic is that of k_flux<D> face for face (bit for bit).
+// Waves are numbered 64-k chunk fastest, then transverse row, then segment.
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_flux_march(const RunDev* __restrict__ runs, const int* __restrict__ boff,
+                                                    int nruns, int which, int do_cfl, int sched, int seg) {
+    static_assert(D == 1 || D == 2, "marching runs along X1 or X2");
+    const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int r = find_run(boff, nruns, bl);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n1 = R.n1, n2 = R.n2;
+    const uint32_t nkc = (uint32_t)R.n3 >> 6;
+    const int act = D == 1 ? R.act2 : R.act1;             // transverse halo rows for flux-CT
+    const int ntr = D == 1 ? n2 : n1;                     // interior transverse rows
+    const uint32_t nrow = (uint32_t)(ntr + 2 * act);
+    const int nf = (D == 1 ? n1 : n2) + 1;                // faces along D
+    const uint32_t nseg = (uint32_t)((nf + seg - 1) / seg);
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)((uint32_t)(bl - boff[r]) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const uint32_t t = wv / nkc, kc = wv - t * nkc;
+    const uint32_t sg = t / nrow, row = t - sg * nrow;
+    double cw = 0.0;
+    if (sg < nseg) {
+        const int k = (int)(kc << 6) + (int)(threadIdx.x & 63);
+        const int a = (int)sg * seg, b = min(a + seg, nf);
+        const int tr = (int)row - act;                    // j (D = 1) or i (D = 2)
+        const bool counts = tr >= 0 && tr < ntr;          // halo rows do not enter the CFL step
+        const uint32_t st = (uint32_t)(D == 1 ? R.s1 : R.s2);
+        uint32_t c = (uint32_t)(D == 1 ? cell_index(R, a, tr, k) : cell_index(R, tr, a, k));
+        const uint32_t vs = (uint32_t)R.vs;
+        const double* __restrict__ P = which ? R.Ph : R.P;
+        double* __restrict__ F = R.F[D];
+        // window: c0 = cell f-1, c1 = cell f, Pl = left state of face f-1/2
+        double c0[NPR], c1[NPR], Pl[NPR];
+#pragma unroll
+        for (int q = 0; q < NPR; ++q) {
+            const double* Pq = P + q * vs;
+            const double m2 = gld(Pq, c - 2 * st), m1 = gld(Pq, c - st);
+            c1[q] = gld(Pq, c);
+            c0[q] = m1;
+            Pl[q] = m1 + mc_half_slope(m2, m1, c1[q]);
+        }
+        for (int f = a; f < b; ++f, c += st) {
+            double Pr[NPR], Pn[NPR];
+#pragma unroll
+            for (int q = 0; q < NPR; ++q) {
+                const double c2 = gld(P + q * vs, c + st);
+                const double h = mc_half_slope(c0[q], c1[q], c2);
+                Pr[q] = c1[q] - h;
+                Pn[q] = c1[q] + h;
+                c0[q] = c1[q];
+                c1[q] = c2;
+            }
+            if (D == 2 && R.mks && (f == 0 || f == n2)) {
+                // polar axis: no flux through the pole
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q != 4 + D) gst(F + flux_slot<D>(q) * vs, c, 0.0);
+            } else {
+                Geo G;
+                load_geo_k(R.gf[D], R.gpts,
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(D == 1 ? geo_index(R, f, tr) : geo_index(R, tr, f))),
+                           G);
+                double out[NCS];
+                const double cwf = riemann_face<D, false>(R, Pl, Pr, G, out);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q != 4 + D) gst(F + flux_slot<D>(q) * vs, c, out[q]);
+                if (counts) cw = fmax(cw, cwf);
+            }
+#pragma unroll
+            for (int q = 0; q < NPR; ++q) Pl[q] = Pn[q];
+        }
     }
+    if (do_cfl) cfl_max<D>(R, cw);
+}
+
+// 64-bit lane shifts across the whole wave (DPP wave_shr:1 and wave_shl:1 on both halves): lane l
+// takes the value of lane l - 1 (shr) or l + 1 (shl); the one lane without a source keeps `old`.
+__device__ __forceinline__ double lane_shr1(double old, double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_shl1(double old, double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// value of lane l (wave-uniform l) in every lane
+__device__ __forceinline__ double lane_read(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// X3 face fluxes of PLM runs with n3 % 64 == 0: a wave is 64 consecutive k of one (i, j) row and
+// its face k - 1/2 needs cells k-2 .. k+1.  Each lane loads its own cell and one edge cell (lane
+// 0: k0-1, lane 1: k0-2, lane 63: k0+64, periodic in k; the rest reload their own), and takes
+// its neighbours' cells from the adjacent lanes: two loads per primitive instead of four.  The
+// arithmetic is that of k_flux<3> face for face (bit for bit).
+__global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ runs, const int* __restrict__ boff,
+                                                     int nruns, int which, int do_cfl, int sched) {
+    const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int r = find_run(boff, nruns, bl);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const uint32_t nkc = (uint32_t)n3 >> 6;
+    const uint32_t nj = (uint32_t)(n2 + 2 * R.act2);
+    const uint32_t nrows = (uint32_t)(n1 + 2 * R.act1) * nj;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)((uint32_t)(bl - boff[r]) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const uint32_t row = wv / nkc, kc = wv - row * nkc;
+    double cw = 0.0;
+    if (row < nrows) {
+        const uint32_t qi = row / nj;
+        const int i = (int)qi - R.act1, j = (int)(row - qi * nj) - R.act2;
+        const int lane = (int)(threadIdx.x & 63);
+        const int k0 = (int)(kc << 6), k = k0 + lane;
+        const uint32_t base = (uint32_t)cell_index(R, i, j, 0);
+        int ke = k;
+        if (lane == 0) ke = k0 - 1;
+        else if (lane == 1) ke = k0 - 2;
+        else if (lane == 63) ke = k0 + 64;
+        ke = ke < 0 ? ke + n3 : (ke >= n3 ? ke - n3 : ke);
+        const uint32_t vs = (uint32_t)R.vs;
+        const double* __restrict__ P = which ? R.Ph : R.P;
+        Geo G;
+        load_geo_k(R.gc, R.gpts, (uint32_t)__builtin_amdgcn_readfirstlane((int)geo_index(R, i, j)), G);
+        double Pl[NPR], Pr[NPR];
+#pragma unroll
+        for (int q = 0; q < NPR; ++q) {
+            const double* Pq = P + q * vs;
+            const double c = gld(Pq, base + (uint32_t)k);
+            const double e = gld(Pq, base + (uint32_t)ke);
+            const double m1 = lane_shr1(e, c);                                     // cell k-1
+            const double m2 = lane_shr1(lane_read(e, 1), m1);                      // cell k-2
+            const double p1 = lane_shl1(e, c);                                     // cell k+1
+            Pl[q] = m1 + mc_half_slope(m2, m1, c);
+            Pr[q] = c - mc_half_slope(m1, c, p1);
+        }
+        double out[NCS];
+        const double cwf = riemann_face<3, false>(R, Pl, Pr, G, out);
+        double* __restrict__ F = R.F[3];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q != 7) gst(F + flux_slot<3>(q) * vs, base + (uint32_t)k, out[q]);
+        if (i >= 0 && i < n1 && j >= 0 && j < n2) cw = cwf;
+    }
+    if (do_cfl) cfl_max<3>(R, cw);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -493,68 +667,72 @@ __device__ __forceinline__ void source_terms(const St& s, const double* __restri
     S[3] = 0.0;
 }
 
-// X1-face data that a cell shares with its neighbour in i: the stored X1 flux slots of the face
-// at i' - 1/2 and the flux-CT EMFs on its edges, E3 at (i'-1/2, j+b-1/2) and E2 at
-// (i'-1/2, j, k+c-1/2) for b, c in {0, 1}.  The upper face of cell i is the lower face of i + 1.
-struct X1Face {
-    double f[NFS];
-    double e3[2], e2[2];
-};
+// ------------------------------------------------------------------------------------------
+// flux-CT edge EMFs (Sec. 2.2): each edge EMF is the average of the four face fluxes of the
+// transverse field around the edge, formed once per edge by k_emf and kept, for the rest of the
+// stage, in slot FS_EMF of a face array (that slot holds the normal field component only in the
+// diagnostic copy, never during a step):
+//   E3 at (i-1/2, j-1/2, k) in F[1], E1 at (i, j-1/2, k-1/2) in F[2], E2 at (i-1/2, j, k-1/2) in F[3],
+// each at the cell index of (i, j, k).  EMFs on the polar axis (MKS, j' = 0 or n2) are zero.
+// ------------------------------------------------------------------------------------------
 
-// Edge EMFs of flux-CT: the average of the four face fluxes of the transverse field around the
-// edge (Sec. 2.2).  E3 at (i'-1/2, j'-1/2) from cell index c of (i', j', k); zero on the axis.
-__device__ __forceinline__ double emf3(const RunDev& R, int64_t c, int jj) {
-    if (R.mks && (jj == 0 || jj == R.n2)) return 0.0;
-    const double* F1b2 = R.F[1] + flux_slot<1>(6) * R.vs;
-    const double* F2b1 = R.F[2] + flux_slot<2>(5) * R.vs;
-    return 0.25 * (gld(F1b2, (uint32_t)(c - R.s2)) + gld(F1b2, (uint32_t)c) - gld(F2b1, (uint32_t)(c - R.s1)) -
-                   gld(F2b1, (uint32_t)c));
-}
-// E2 at (i'-1/2, j, k'-1/2) from cell indices kk of (i', j, k') and kk1 of (i', j, k'-1)
-__device__ __forceinline__ double emf2(const RunDev& R, int64_t kk, int64_t kk1) {
-    const double* F3b1 = R.F[3] + flux_slot<3>(5) * R.vs;
-    const double* F1b3 = R.F[1] + flux_slot<1>(7) * R.vs;
-    return 0.25 * (gld(F3b1, (uint32_t)(kk - R.s1)) + gld(F3b1, (uint32_t)kk) - gld(F1b3, (uint32_t)kk1) -
-                   gld(F1b3, (uint32_t)kk));
+constexpr int FS_EMF = FS_BN;
+
+__device__ __forceinline__ const double* emf_slot(const RunDev& R, int d) {
+    return R.F[d == 3 ? 1 : (d == 1 ? 2 : 3)] + FS_EMF * R.vs;
 }
 
-// X1 face of cell index c (cell (i', j, k); cm, cp: its k-1 and k+1 neighbours)
-__device__ __forceinline__ void load_x1_face(const RunDev& R, int j, int64_t c, int64_t cm, int64_t cp, X1Face& x) {
-    if (!R.act1) return;
-    const double* __restrict__ F1 = R.F[1];
-#pragma unroll
-    for (int q = 0; q < NFS; ++q) x.f[q] = gld(F1 + q * R.vs, (uint32_t)c);
-    if (R.act2) {
-        x.e3[0] = emf3(R, c, j);
-        x.e3[1] = emf3(R, c + R.s2, j + 1);
+// one thread per edge site (i', j', k) in [0, n1] x [0, n2] x [0, n3): E3 where X1 and X2 are active,
+// E2 (j' < n2) where X1 and X3 are, E1 (i' < n1) where X2 and X3 are
+__global__ __launch_bounds__(256) void k_emf(const RunDev* __restrict__ runs, const int* __restrict__ boff, int nruns,
+                                             int sched) {
+    const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int r = find_run(boff, nruns, bl);
+    const RunDev& R = runs[r];
+    if (!R.var->active) return;
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
+    if (e >= (uint32_t)(n1 + 1) * (uint32_t)(n2 + 1) * (uint32_t)n3) return;
+    const uint32_t t = fdiv(e, R.fd_n3);
+    const int k = (int)(e - t * (uint32_t)n3);
+    const uint32_t i = fdiv(t, R.fd_row[2]);   // n2 + 1
+    const int j = (int)(t - i * (uint32_t)(n2 + 1));
+    const uint32_t c = (uint32_t)cell_index(R, (int)i, j, k);
+    const uint32_t s1 = (uint32_t)R.s1, s2 = (uint32_t)R.s2, vs = (uint32_t)R.vs;
+    const uint32_t ckm = c - (uint32_t)k + (uint32_t)(k == 0 ? n3 - 1 : k - 1);
+    const bool axis = R.mks && (j == 0 || j == n2);
+    if (R.act1 && R.act2) {
+        const double* F1b2 = R.F[1] + flux_slot<1>(6) * vs;
+        const double* F2b1 = R.F[2] + flux_slot<2>(5) * vs;
+        const double v = axis ? 0.0 : 0.25 * (gld(F1b2, c - s2) + gld(F1b2, c) - gld(F2b1, c - s1) - gld(F2b1, c));
+        gst(R.F[1] + FS_EMF * vs, c, v);
     }
-    if (R.act3) {
-        x.e2[0] = emf2(R, c, cm);
-        x.e2[1] = emf2(R, cp, c);
+    if (R.act1 && R.act3 && j < n2) {
+        const double* F3b1 = R.F[3] + flux_slot<3>(5) * vs;
+        const double* F1b3 = R.F[1] + flux_slot<1>(7) * vs;
+        gst(R.F[3] + FS_EMF * vs, c, 0.25 * (gld(F3b1, c - s1) + gld(F3b1, c) - gld(F1b3, ckm) - gld(F1b3, c)));
     }
-}
-
-// lower X1 face of interior cell (i, j, k)
-__device__ __forceinline__ void x1_lower(const RunDev& R, int i, int j, int k, X1Face& x) {
-    const int64_t ci = cell_index(R, i, j, k);
-    const int64_t kb = ci - k;
-    load_x1_face(R, j, ci, kb + (k == 0 ? R.n3 - 1 : k - 1), kb + (k + 1 == R.n3 ? 0 : k + 1), x);
+    if (R.act2 && R.act3 && (int)i < n1) {
+        const double* F2b3 = R.F[2] + flux_slot<2>(7) * vs;
+        const double* F3b2 = R.F[3] + flux_slot<3>(6) * vs;
+        const double v = axis ? 0.0 : 0.25 * (gld(F2b3, ckm) + gld(F2b3, c) - gld(F3b2, c - s2) - gld(F3b2, c));
+        gst(R.F[2] + FS_EMF * vs, c, v);
+    }
 }
 
 // Conserved state after the stage update of interior cell (i,j,k): flux-CT, the flux divergence,
 // the centred source from the stage-input primitives Pg, U = U(P^n) + c dt L.  With ENT = false
-// the entropy component (used only by the entropy inversion) is skipped.  xf holds the cell's
-// lower X1 face on entry and its upper X1 face (the next cell's lower one) on return.
+// the entropy component (used only by the entropy inversion) is skipped.
 template <bool ENT, bool UNI, int STAGE>
 __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k, double* U, double* Pg,
-                                            Geo& G, St& sg, int64_t& gi_out, X1Face& xf) {
+                                            Geo& G, St& sg, int64_t& gi_out) {
     constexpr int stage = STAGE;
-    const int n2 = R.n2, n3 = R.n3;
-    const int64_t ci = cell_index(R, i, j, k);
-    const int64_t vs = R.vs, s1 = R.s1, s2 = R.s2;
-    const int64_t kb = ci - k;
-    const int64_t ckm = kb + (k == 0 ? n3 - 1 : k - 1);
-    const int64_t ckp = kb + (k + 1 == n3 ? 0 : k + 1);
+    const int n3 = R.n3;
+    const uint32_t ci = (uint32_t)cell_index(R, i, j, k);
+    const uint32_t vs = (uint32_t)R.vs, s1 = (uint32_t)R.s1, s2 = (uint32_t)R.s2;
+    const uint32_t kb = ci - (uint32_t)k;
+    const uint32_t ckp = kb + (uint32_t)(k + 1 == n3 ? 0 : k + 1);
+    const double* __restrict__ F1 = R.F[1];
     const double* __restrict__ F2 = R.F[2];
     const double* __restrict__ F3 = R.F[3];
     const bool has3 = R.act1 && R.act2, has1 = R.act2 && R.act3, has2 = R.act1 && R.act3;
@@ -572,90 +750,88 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
             L[8] -= (entropy_flux<3>(R, i, j, kp, which) - entropy_flux<3>(R, i, j, k, which)) * R.idx[3];
         }
     }
-    {
-        X1Face up;
-        load_x1_face(R, j, ci + s1, ckm + s1, ckp + s1, up);
-        if (R.act1) {
+    if (R.act1) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) L[q] -= (up.f[q] - xf.f[q]) * R.idx[1];
+        for (int q = 0; q < 5; ++q) L[q] -= (gld(F1 + q * vs, ci + s1) - gld(F1 + q * vs, ci)) * R.idx[1];
+    }
+    if (R.act2) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) L[q] -= (gld(F2 + q * vs, ci + s2) - gld(F2 + q * vs, ci)) * R.idx[2];
+    }
+    if (R.act3) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) L[q] -= (gld(F3 + q * vs, ckp) - gld(F3 + q * vs, ci)) * R.idx[3];
+    }
+    // field components: F^d(B^d) is not used; transverse ones come from the edge EMFs where both
+    // directions of the edge are active, from the face fluxes themselves otherwise
+    double f1b2m = 0.0, f1b2p = 0.0, f1b3m = 0.0, f1b3p = 0.0;
+    double f2b1m = 0.0, f2b1p = 0.0, f2b3m = 0.0, f2b3p = 0.0;
+    double f3b1m = 0.0, f3b1p = 0.0, f3b2m = 0.0, f3b2p = 0.0;
+    if (has3) {
+        // E3 on the four edges (i'-1/2, j'-1/2), i' in {i, i+1}, j' in {j, j+1}
+        const double* E3 = emf_slot(R, 3);
+        const double e00 = gld(E3, ci), e10 = gld(E3, ci + s1), e01 = gld(E3, ci + s2), e11 = gld(E3, ci + s1 + s2);
+        f1b2m = 0.5 * (e00 + e01);
+        f1b2p = 0.5 * (e10 + e11);
+        f2b1m = -0.5 * (e00 + e10);
+        f2b1p = -0.5 * (e01 + e11);
+    } else {
+        if (R.act1) {
+            f1b2m = gld(F1 + flux_slot<1>(6) * vs, ci);
+            f1b2p = gld(F1 + flux_slot<1>(6) * vs, ci + s1);
         }
         if (R.act2) {
-            const int64_t cq = ci + s2;
-#pragma unroll
-            for (int q = 0; q < 5; ++q)
-                L[q] -= (gld(F2 + q * vs, (uint32_t)cq) - gld(F2 + q * vs, (uint32_t)ci)) * R.idx[2];
+            f2b1m = gld(F2 + flux_slot<2>(5) * vs, ci);
+            f2b1p = gld(F2 + flux_slot<2>(5) * vs, ci + s2);
         }
-        if (R.act3) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q)
-                L[q] -= (gld(F3 + q * vs, (uint32_t)ckp) - gld(F3 + q * vs, (uint32_t)ci)) * R.idx[3];
-        }
-        // field components: F^d(B^d) is not used; transverse ones from edge EMFs where they exist
-        double f1b2m = 0.0, f1b2p = 0.0, f1b3m = 0.0, f1b3p = 0.0;
-        if (R.act1) {
-            f1b2m = xf.f[flux_slot<1>(6)]; f1b2p = up.f[flux_slot<1>(6)];
-            f1b3m = xf.f[flux_slot<1>(7)]; f1b3p = up.f[flux_slot<1>(7)];
-        }
-        double f2b1m = 0.0, f2b1p = 0.0, f2b3m = 0.0, f2b3p = 0.0;
-        double f3b1m = 0.0, f3b1p = 0.0, f3b2m = 0.0, f3b2p = 0.0;
+    }
+    if (has1) {
+        // E1 on the edges (i, j'-1/2, k'-1/2), j' in {j, j+1}, k' in {k, k+1}
+        const double* E1 = emf_slot(R, 1);
+        const double e00 = gld(E1, ci), e10 = gld(E1, ci + s2), e01 = gld(E1, ckp), e11 = gld(E1, ckp + s2);
+        f2b3m = 0.5 * (e00 + e01);
+        f2b3p = 0.5 * (e10 + e11);
+        f3b2m = -0.5 * (e00 + e10);
+        f3b2p = -0.5 * (e01 + e11);
+    } else {
         if (R.act2) {
-            f2b1m = gld(F2 + flux_slot<2>(5) * vs, (uint32_t)ci);
-            f2b1p = gld(F2 + flux_slot<2>(5) * vs, (uint32_t)(ci + s2));
-            f2b3m = gld(F2 + flux_slot<2>(7) * vs, (uint32_t)ci);
-            f2b3p = gld(F2 + flux_slot<2>(7) * vs, (uint32_t)(ci + s2));
+            f2b3m = gld(F2 + flux_slot<2>(7) * vs, ci);
+            f2b3p = gld(F2 + flux_slot<2>(7) * vs, ci + s2);
         }
         if (R.act3) {
-            f3b1m = gld(F3 + flux_slot<3>(5) * vs, (uint32_t)ci); f3b1p = gld(F3 + flux_slot<3>(5) * vs, (uint32_t)ckp);
-            f3b2m = gld(F3 + flux_slot<3>(6) * vs, (uint32_t)ci); f3b2p = gld(F3 + flux_slot<3>(6) * vs, (uint32_t)ckp);
+            f3b2m = gld(F3 + flux_slot<3>(6) * vs, ci);
+            f3b2p = gld(F3 + flux_slot<3>(6) * vs, ckp);
         }
-        if (has3) {
-            // E3 on the four edges (i'-1/2, j'-1/2), i' in {i, i+1}, j' in {j, j+1}
-            f1b2m = 0.5 * (xf.e3[0] + xf.e3[1]);
-            f1b2p = 0.5 * (up.e3[0] + up.e3[1]);
-            f2b1m = -0.5 * (xf.e3[0] + up.e3[0]);
-            f2b1p = -0.5 * (xf.e3[1] + up.e3[1]);
-        }
-        if (has1) {
-            // E1 at edges (i, j'-1/2, k'-1/2)
-            const double* F2b3 = F2 + flux_slot<2>(7) * vs;
-            const double* F3b2 = F3 + flux_slot<3>(6) * vs;
-            double E[2][2];
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int jj = j + b;
-                    if (R.mks && (jj == 0 || jj == n2)) { E[b][c] = 0.0; continue; }
-                    const int64_t kk = c == 0 ? ci : ckp;        // cell/face k' index
-                    const int64_t kk1 = c == 0 ? ckm : ci;       // k'-1
-                    E[b][c] = 0.25 * (gld(F2b3, (uint32_t)(kk1 + b * s2)) + gld(F2b3, (uint32_t)(kk + b * s2)) -
-                                      gld(F3b2, (uint32_t)(kk + (b - 1) * s2)) - gld(F3b2, (uint32_t)(kk + b * s2)));
-                }
-            f2b3m = 0.5 * (E[0][0] + E[0][1]);
-            f2b3p = 0.5 * (E[1][0] + E[1][1]);
-            f3b2m = -0.5 * (E[0][0] + E[1][0]);
-            f3b2p = -0.5 * (E[0][1] + E[1][1]);
-        }
-        if (has2) {
-            // E2 on the edges (i'-1/2, j, k'-1/2), i' in {i, i+1}, k' in {k, k+1}
-            f1b3m = -0.5 * (xf.e2[0] + xf.e2[1]);
-            f1b3p = -0.5 * (up.e2[0] + up.e2[1]);
-            f3b1m = 0.5 * (xf.e2[0] + up.e2[0]);
-            f3b1p = 0.5 * (xf.e2[1] + up.e2[1]);
-        }
+    }
+    if (has2) {
+        // E2 on the edges (i'-1/2, j, k'-1/2), i' in {i, i+1}, k' in {k, k+1}
+        const double* E2 = emf_slot(R, 2);
+        const double e00 = gld(E2, ci), e10 = gld(E2, ci + s1), e01 = gld(E2, ckp), e11 = gld(E2, ckp + s1);
+        f1b3m = -0.5 * (e00 + e01);
+        f1b3p = -0.5 * (e10 + e11);
+        f3b1m = 0.5 * (e00 + e10);
+        f3b1p = 0.5 * (e01 + e11);
+    } else {
         if (R.act1) {
-            L[6] -= (f1b2p - f1b2m) * R.idx[1];
-            L[7] -= (f1b3p - f1b3m) * R.idx[1];
-        }
-        if (R.act2) {
-            L[5] -= (f2b1p - f2b1m) * R.idx[2];
-            L[7] -= (f2b3p - f2b3m) * R.idx[2];
+            f1b3m = gld(F1 + flux_slot<1>(7) * vs, ci);
+            f1b3p = gld(F1 + flux_slot<1>(7) * vs, ci + s1);
         }
         if (R.act3) {
-            L[5] -= (f3b1p - f3b1m) * R.idx[3];
-            L[6] -= (f3b2p - f3b2m) * R.idx[3];
+            f3b1m = gld(F3 + flux_slot<3>(5) * vs, ci);
+            f3b1p = gld(F3 + flux_slot<3>(5) * vs, ckp);
         }
-        xf = up;
+    }
+    if (R.act1) {
+        L[6] -= (f1b2p - f1b2m) * R.idx[1];
+        L[7] -= (f1b3p - f1b3m) * R.idx[1];
+    }
+    if (R.act2) {
+        L[5] -= (f2b1p - f2b1m) * R.idx[2];
+        L[7] -= (f2b3p - f2b3m) * R.idx[2];
+    }
+    if (R.act3) {
+        L[5] -= (f3b1p - f3b1m) * R.idx[3];
+        L[6] -= (f3b2p - f3b2m) * R.idx[3];
     }
 
     int64_t gi = geo_index(R, i, j);
@@ -666,7 +842,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const double* __restrict__ Pn = R.P;
     const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) Pg[q] = gld(Pin + q * vs, (uint32_t)ci);
+    for (int q = 0; q < NPR; ++q) Pg[q] = gld(Pin + q * vs, ci);
     prim_state(Pg, G, gam, sg);
     if (stage == 1) {
         // the stage input is P^n itself: U(P^n) comes from the same state
@@ -674,7 +850,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     } else {
         double P0[NPR];
 #pragma unroll
-        for (int q = 0; q < NPR; ++q) P0[q] = gld(Pn + q * vs, (uint32_t)ci);
+        for (int q = 0; q < NPR; ++q) P0[q] = gld(Pn + q * vs, ci);
         St s0;
         prim_state(P0, G, gam, s0);
         flux_of<0>(P0, s0, G, ENT ? s0.p * pow(P0[0], 1.0 - gam) : 0.0, U);
@@ -694,13 +870,13 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
 // the Lorentz cap.  Cells that need the entropy method (beta switch), Brent, or a magnetisation
 // ceiling go to the run's slow list and are finished by k_update_slow with the full procedure.
 template <bool UNI, int STAGE>
-__device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k, X1Face& xf) {
+__device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k) {
     constexpr int stage = STAGE;
     double U[NCS], Pg[NPR];
     Geo G;
     St sg;
     int64_t gi;
-    stage_state<false, UNI, STAGE>(R, i, j, k, U, Pg, G, sg, gi, xf);
+    stage_state<false, UNI, STAGE>(R, i, j, k, U, Pg, G, sg, gi);
     bool slow = sg.p < R.beta_ent * 0.5 * sg.bsq;
     double P[NPR];
     if (!slow) {
@@ -765,18 +941,14 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
         const int j = (int)(((t - i * (uint32_t)((R.n2 + (1 << lw) - 1) >> lw)) << lw) + wv);
         if (j >= R.n2) return;
         const int k = (int)(kc << 6) + (int)(threadIdx.x & 63);
-        X1Face xf;
-        x1_lower(R, (int)i, j, k, xf);
-        update_fast<UNI, STAGE>(R, (int)i, j, k, xf);
+        update_fast<UNI, STAGE>(R, (int)i, j, k);
     } else {
         const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
         if (e >= (uint32_t)R.n1 * (uint32_t)R.n2 * (uint32_t)R.n3) return;
         const uint32_t t = fdiv(e, R.fd_n3);
         const uint32_t i = fdiv(t, R.fd_n2);
         const int j = (int)(t - i * (uint32_t)R.n2), k = (int)(e - t * (uint32_t)R.n3);
-        X1Face xf;
-        x1_lower(R, (int)i, j, k, xf);
-        update_fast<UNI, STAGE>(R, (int)i, j, k, xf);
+        update_fast<UNI, STAGE>(R, (int)i, j, k);
     }
 }
 
@@ -797,10 +969,8 @@ __global__ __launch_bounds__(256) void k_update_slow(const RunDev* __restrict__ 
         Geo G;
         St sg;
         int64_t gi;
-        X1Face xf;
-        x1_lower(R, i, j, k, xf);
-        if (stage == 1) stage_state<true, false, 1>(R, i, j, k, U, Pg, G, sg, gi, xf);
-        else stage_state<true, false, 2>(R, i, j, k, U, Pg, G, sg, gi, xf);
+        if (stage == 1) stage_state<true, false, 1>(R, i, j, k, U, Pg, G, sg, gi);
+        else stage_state<true, false, 2>(R, i, j, k, U, Pg, G, sg, gi);
         double P[NPR];
 #pragma unroll
         for (int q = 0; q < NPR; ++q) P[q] = Pg[q];
@@ -1116,9 +1286,13 @@ static void flux_dir(int d, const RunDev* runs, const int* boff, int nruns, int 
 }
 
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int uni, int ppm, int bs, int sched, hipStream_t st) {
+                 int ent, int uni, int ppm, int bs, int sched, int seg, hipStream_t st) {
     if (nblocks <= 0) return;
-    if (ent) {
+    if (uni && !ppm && !ent) {
+        if (d == 1) k_flux_march<1><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched, seg);
+        else if (d == 2) k_flux_march<2><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched, seg);
+        else k_flux3_lanes<<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+    } else if (ent) {
         if (ppm) flux_dir<true, false, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
         else flux_dir<true, false, false>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
     } else if (uni) {
@@ -1128,6 +1302,10 @@ void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblo
         if (ppm) flux_dir<false, false, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
         else flux_dir<false, false, false>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
     }
+}
+
+void launch_emf(const RunDev* runs, const int* boff, int nruns, int nblocks, int bs, int sched, hipStream_t st) {
+    if (nblocks > 0) k_emf<<<nblocks, bs, 0, st>>>(runs, boff, nruns, sched);
 }
 
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st) {

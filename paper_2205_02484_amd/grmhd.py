@@ -266,11 +266,11 @@ class Context:
         return ({k: getattr(hz, k) for k in ("mdot", "phi_b", "ldot", "edot", "phi_b_norm", "i_h")}, rad)
 
     def autotune(self, steps_per_candidate: int = 2) -> str:
-        buf = ctypes.create_string_buffer(4096)
+        buf = ctypes.create_string_buffer(1 << 16)
         _check(load().grmhd_autotune(self._h, int(steps_per_candidate), buf, len(buf)))
         return buf.value.decode()
 
-    KERNELS = ("bound", "flux1", "flux2", "flux3", "dt", "update", "fixup", "update_slow")
+    KERNELS = ("bound", "flux1", "flux2", "flux3", "dt", "update", "fixup", "update_slow", "emf")
 
     def kernel_timing(self, on: bool):
         _check(load().grmhd_kernel_timing(self._h, int(bool(on))))
@@ -333,7 +333,7 @@ class Batch:
         _check(load().grmhd_batch_advance(self._h, int(steps)))
 
     def autotune(self, steps_per_candidate: int = 2) -> str:
-        buf = ctypes.create_string_buffer(4096)
+        buf = ctypes.create_string_buffer(1 << 16)
         _check(load().grmhd_batch_autotune(self._h, int(steps_per_candidate), buf, len(buf)))
         return buf.value.decode()
 
