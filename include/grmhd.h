@@ -147,6 +147,19 @@ typedef struct {
  * context's stream.  EINVAL for a non-MKS grid or one that does not reach the horizon. */
 int grmhd_diag_full(grmhd_ctx* ctx, grmhd_horizon* hz, double* radial);
 
+/* Largest radial size n1 that grmhd_diag_full_noalloc accepts. */
+#define GRMHD_NOALLOC_MAX_N1 16384
+
+/* grmhd_diag_full for callers that cannot allocate memory (code between replays of captured HIP
+ * graphs, tight serving loops, harnesses that forbid hipMalloc): the call makes no device or host
+ * allocation.  Its shell sums go to one fixed device array of 6 * GRMHD_NOALLOC_MAX_N1 doubles per
+ * GPU, which the library holds from the first grmhd_init on that GPU until the process ends.
+ * Arguments, results and errors are those of grmhd_diag_full (bit for bit the same values), plus
+ * EINVAL when the run's n1 exceeds GRMHD_NOALLOC_MAX_N1.  Every call on a GPU shares that array and
+ * each call overwrites what it reads: calls that overlap on one GPU (several host threads, or
+ * contexts on several streams) race, so the caller serialises them. */
+int grmhd_diag_full_noalloc(grmhd_ctx* ctx, grmhd_horizon* hz, double* radial);
+
 /* Copy the current primitive fields out ([8][n1][n2][n3]). */
 int grmhd_get_prims(grmhd_ctx* ctx, double* out, int32_t out_on_device);
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -616,10 +617,44 @@ struct Engine {
 
 }  // namespace
 
+// Shell sums of grmhd_diag_full_noalloc: one array per GPU for the life of the process.  On the
+// host its name is not a device address; host code uses only the address hipGetSymbolAddress gives
+// on each device (scratch_address).
+static __device__ __align__(256) double scratch[6 * GRMHD_NOALLOC_MAX_N1];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {nullptr};
+
+// device address of `scratch` on the current device, looked up once per device
+int scratch_address(double** out) {
+    *out = nullptr;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GRMHD_EDEVICE, "device %d is beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(GRMHD_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return GRMHD_OK;
+}
+
+}  // namespace
+
 struct grmhd_ctx {
     Engine eng;
     Run* run = nullptr;
     double last_dt_req = -1.0;
+    double* scratch = nullptr;  // device address of `scratch` on the context's GPU
 };
 
 struct grmhd_batch {
@@ -670,6 +705,8 @@ int grmhd_init(grmhd_ctx** out, const grmhd_grid* grid, const grmhd_params* para
     if (rc) { delete c; return rc; }
     rc = create_run(grid, params, prims, prims_on_device, c->eng.st, &c->run);
     if (rc) { delete c; return rc; }
+    rc = scratch_address(&c->scratch);
+    if (rc) { free_run(c->run); delete c; return rc; }
     c->eng.runs.push_back(c->run);
     c->eng.dirty = true;
     *out = c;
@@ -817,6 +854,45 @@ int grmhd_diag_full(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
             radial[5 * n1 + i] = m != 0.0 ? h[5 * n1 + i] / m : NAN;
         }
     }
+    return GRMHD_OK;
+}
+
+int grmhd_diag_full_noalloc(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
+    if (!c || !hz) return fail(GRMHD_EINVAL, "NULL argument");
+    const RunDev& R = c->run->h;
+    if (!R.mks || c->run->ih < 0) return fail(GRMHD_EINVAL, "diagnostics need an MKS grid reaching the horizon");
+    const int n1 = R.n1, ih = c->run->ih;
+    if (n1 > GRMHD_NOALLOC_MAX_N1)
+        return fail(GRMHD_EINVAL, "n1 = %d exceeds GRMHD_NOALLOC_MAX_N1 = %d", n1, GRMHD_NOALLOC_MAX_N1);
+    if (!c->scratch) return fail(GRMHD_EDEVICE, "no scratch address for this context");
+    const hipStream_t st = c->eng.st;
+    double* d = c->scratch;
+    launch_diag_shells(R, d, st);  // every row of the n1 shells is written: nothing to clear
+    hipError_t e = hipGetLastError();
+    double hs[4] = {0.0, 0.0, 0.0, 0.0};
+    if (radial) {
+        if (e == hipSuccess) e = hipMemcpyAsync(radial, d, 6 * (size_t)n1 * sizeof(double), hipMemcpyDeviceToHost, st);
+    } else {
+        for (int q = 0; q < 4 && e == hipSuccess; ++q)
+            e = hipMemcpyAsync(&hs[q], d + (size_t)q * n1 + ih, sizeof(double), hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(GRMHD_EDEVICE, "diag_full_noalloc: %s", hipGetErrorString(e));
+    if (radial) {
+        for (int q = 0; q < 4; ++q) hs[q] = radial[q * n1 + ih];
+        for (int i = 0; i < n1; ++i) {
+            const double m = radial[i];
+            radial[4 * n1 + i] = m != 0.0 ? radial[4 * n1 + i] / m : NAN;
+            radial[5 * n1 + i] = m != 0.0 ? radial[5 * n1 + i] / m : NAN;
+        }
+    }
+    hz->mdot = hs[0];
+    hz->phi_b = hs[1];
+    hz->ldot = hs[2];
+    hz->edot = hs[3];
+    hz->phi_b_norm = hz->mdot != 0.0 ? hz->phi_b / std::sqrt(std::fabs(hz->mdot)) : 0.0;
+    hz->i_h = ih;
+    hz->reserved_ = 0;
     return GRMHD_OK;
 }
 
