@@ -145,11 +145,16 @@ __device__ __forceinline__ void velocity_out(const Inv& q, const Geo& G, double 
     P[4] = f * (q.Qu3 + g * q.Bc3);
 }
 
-// 2D Newton-Raphson on (W, v^2); true when |dW| < tol W.
+// 2D Newton-Raphson on (W, v^2); true when |dW| < tol W.  Each lane stops at its own iterate (state
+// set), and the wave leaves the loop only when no lane iterates any more: the exit is wave-uniform.
+// (Inlined inside an enclosing loop, the form with a return per exit made every lane run to maxit
+// and report no convergence; the uniform exit does not depend on how the loop is nested.)
 __device__ __forceinline__ bool newton2d(const Inv& q, double tol, int maxit, double& W, double& v2) {
     const double gg = q.gg;
     const double qb2 = q.QdB * q.QdB;
+    int state = 0;  // 0: iterating, 1: converged, -1: failed
     for (int it = 0; it < maxit; ++it) {
+      if (state == 0) {
         const double bw = q.Bsq + W;
         const double iW = 1.0 / W;
         const double iW2 = iW * iW;
@@ -167,10 +172,12 @@ __device__ __forceinline__ bool newton2d(const Inv& q, double tol, int maxit, do
         const double dv = -(j11 * f2 - j21 * f1) * idet;
         W += dW;
         v2 = fmin(fmax(v2 + dv, 0.0), V2MAX);
-        if (!isfinite(W) || !isfinite(v2) || W <= 0.0) return false;
-        if (fabs(dW) < tol * fabs(W)) return true;
+        if (!isfinite(W) || !isfinite(v2) || W <= 0.0) state = -1;
+        else if (fabs(dW) < tol * fabs(W)) state = 1;
+      }
+      if (!__any(state == 0)) break;
     }
-    return false;
+    return state == 1;
 }
 
 // Primitives from a root (W, v^2) of the energy equations, v^2 in [0, 1 - 1e-12]; false when the
