@@ -92,6 +92,8 @@ def units_per_launch(kind, n1, n2, n3, recon="plm"):
         return (n1 + 2) * (n2 + 2) * n3
     if kind == "update":
         return n1 * n2 * n3
+    if kind == "emf":
+        return (n1 + 1) * (n2 + 1) * n3
     if kind == "bound":
         g = 3 if recon == "ppm" else 2     # ghost layers a run fills
         return (2 * g * (n2 + 2 * g) + 2 * g * n1) * n3
@@ -144,7 +146,8 @@ def ensemble_legs(args, stream):
         "batched_autotune": bat["autotune"],
         "served": {"duration_s": args.serve_seconds, "rate_hz": rate, "load": 0.8, "jobs": srv["jobs"],
                    "p50_s": srv["p50_s"], "p99_s": srv["p99_s"], "mean_s": srv["mean_s"],
-                   "zu_per_s": srv["zu_per_s"], "seconds": srv["seconds"],
+                   "zu_per_s": srv["zu_per_s"], "seconds": srv["seconds"], "passes": srv["passes"],
+                   "max_steps_per_pass": 20,
                    "mix": "2D 128^2 or 3D N^3 (N in [64,160]), 100-2000 steps each"},
     }
 

@@ -169,16 +169,20 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
 
     Arrived jobs wait in a FIFO queue; every pass admits, in order, each queued job whose
     footprint fits the remaining budget (smaller jobs may pass a large head), advances all active
-    jobs by `steps_per_launch` steps, and retires finished ones (fetch + release).  Latency is
-    arrival -> finished on the host.  `batch`, `make_input`, `clock` and `sleep` can be replaced
-    (host-side tests of the scheduling logic)."""
+    jobs, and retires finished ones (fetch + release).  A pass lasts as many steps as the active
+    job closest to completion still needs, at most `steps_per_launch`: a job is retired at the end
+    of the pass in which it takes its last step, never a partial pass later.  Latency is arrival ->
+    finished on the host.  `batch`, `make_input`, `clock` and `sleep` can be replaced (host-side
+    tests of the scheduling logic)."""
     b = batch if batch is not None else grmhd.Batch(budget_bytes=budget_bytes, stream=stream)
     time_now = clock
     pending = sorted(jobs, key=lambda j: j.arrival)
     inputs: Dict[int, np.ndarray] = {}
     queue: List[Job] = []
     active: Dict[int, Job] = {}
+    left: Dict[int, int] = {}          # steps each active job still takes
     finished: List[Job] = []
+    passes = 0
     t0 = time_now()
     nxt = 0
     zu = 0
@@ -199,12 +203,18 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
             j.handle = h
             j.admitted = time_now() - t0
             active[h] = j
+            left[h] = j.nsteps
             del inputs[j.jid]
         queue = still
         if active:
-            b.advance(steps_per_launch)
+            nstep = max(1, min(steps_per_launch, min(left.values())))
+            b.advance(nstep)
+            passes += 1
+            for h in left:
+                left[h] = max(0, left[h] - nstep)
             for h in b.poll():
                 j = active.pop(h)
+                left.pop(h, None)
                 b.fetch(h)
                 b.release(h)
                 j.done = time_now() - t0
@@ -221,7 +231,7 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
     if batch is None:
         b.close()
     lat = np.array([j.done - j.arrival for j in finished])
-    return {"jobs": len(finished), "seconds": el, "zone_updates": zu, "zu_per_s": zu / el,
+    return {"jobs": len(finished), "seconds": el, "zone_updates": zu, "zu_per_s": zu / el, "passes": passes,
             "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
             "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
             "mean_s": float(lat.mean()) if len(lat) else math.nan}

@@ -103,3 +103,18 @@ def test_ensemble_and_served_streams_are_seeded():
     s = serve.served_jobs(rate_hz=1.0, duration_s=30.0, seed=5)
     assert all(100 <= j.nsteps <= 2000 for j in s)
     assert all(x.arrival < y.arrival for x, y in zip(s, s[1:]))
+
+
+def test_a_pass_ends_when_the_nearest_job_takes_its_last_step():
+    """Passes last min(steps_per_launch, fewest steps any active job still takes): each job is
+    retired after exactly its own steps (1 ms of the fake clock per step), never a partial pass
+    later."""
+    clock = FakeClock()
+    fb = FakeBatch(budget=10 * 64 * 64, clock=clock)
+    jobs = [_job(0, 64, 25, arrival=0.0), _job(1, 64, 37, arrival=0.0)]
+    res = serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
+                      sleep=clock.sleep)
+    assert res["jobs"] == 2
+    assert abs(jobs[0].done - jobs[0].admitted - 0.025) < 1e-12
+    assert abs(jobs[1].done - jobs[1].admitted - 0.037) < 1e-12
+    assert res["passes"] == 5      # 10, 10, 5 (job 0 done), 10, 2 (job 1 done)
