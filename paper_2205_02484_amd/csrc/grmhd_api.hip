@@ -364,10 +364,19 @@ struct Engine {
     double t_ms[NTK] = {0};
     long long t_n[NTK] = {0};
     Shape shape[NK];
+    // the X2 and X3 face kernels run on two side streams, forked from and joined back into the
+    // run's stream (parallel branches of the captured graph); default priority like the main one
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
 
     ~Engine() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         drop_graph();
+        for (int x = 0; x < 2; ++x) {
+            if (join_ev[x]) (void)hipEventDestroy(join_ev[x]);
+            if (side[x]) (void)hipStreamDestroy(side[x]);
+        }
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
         if (d_runs) (void)hipFree(d_runs);
         if (d_boff) (void)hipFree(d_boff);
         if (own_stream && st) (void)hipStreamDestroy(st);
@@ -387,6 +396,11 @@ struct Engine {
         }
         const char* ng = std::getenv("GRMHD_NO_GRAPH");
         use_graph = !(ng && ng[0] == '1');
+        HIPCHK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+        for (int x = 0; x < 2; ++x) {
+            HIPCHK(hipStreamCreateWithFlags(&side[x], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&join_ev[x], hipEventDisableTiming));
+        }
         return GRMHD_OK;
     }
     static int64_t elems(const RunDev& R, int kind, int bs, int seg) {
@@ -481,18 +495,33 @@ struct Engine {
             launch_bound(d_runs, boff(KB_BOUND), n, nblk[KB_BOUND], which, shape[KB_BOUND].bs,
                          shape[KB_BOUND].sched, st);
             mark(TK_BOUND);
+            // face kernels: one direction after another while timing each kernel, otherwise X1 on
+            // the run's stream and X2, X3 on the side streams (independent: each reads the stage
+            // input and writes its own face array and CFL slot)
+            const bool fork = !timing;
+            if (fork) {
+                HIPCHK(hipEventRecord(fork_ev, st));
+                for (int x = 0; x < 2; ++x) HIPCHK(hipStreamWaitEvent(side[x], fork_ev, 0));
+            }
             for (int d = 1; d <= 3; ++d) {
                 int any = 0;
                 for (int v = 0; v < 4; ++v) any += nblk[flux_kind(d, v & 1, v >> 1)] > 0;
                 if (!any) continue;
+                const hipStream_t sd = (fork && d > 1) ? side[d - 2] : st;
                 mark(TK_FLUX1 + d - 1);
                 for (int v = 0; v < 4; ++v) {
                     const bool uni = v & 1, ppm = v >> 1;
                     const int k = flux_kind(d, uni, ppm);
                     launch_flux(d, d_runs, boff(k), n, nblk[k], which, stage == 1, 0, uni, ppm, shape[k].bs,
-                                shape[k].sched, shape[k].seg, st);
+                                shape[k].sched, shape[k].seg, sd);
                 }
                 mark(TK_FLUX1 + d - 1);
+            }
+            if (fork) {
+                for (int x = 0; x < 2; ++x) {
+                    HIPCHK(hipEventRecord(join_ev[x], side[x]));
+                    HIPCHK(hipStreamWaitEvent(st, join_ev[x], 0));
+                }
             }
             if (stage == 1) {
                 mark(TK_DT);
