@@ -37,8 +37,8 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(GRMHD_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
     } while (0)
 
-// block tables: ghosts; fluxes per direction and update, each once over the runs with n3 % 64 == 0
-// (a wave's cells share (r, theta): scalar metric loads) and once over the other runs; the flux
+// block tables: ghosts; fluxes per direction and update, each once over the row-path runs (a wave
+// is one phi row, its cells share (r, theta): scalar metric loads) and once over the other runs; the flux
 // tables also split PLM runs (KB_F*) from PPM runs (KB_P*), which have kernels of their own
 enum {
     KB_BOUND = 0,
@@ -282,11 +282,16 @@ int create_run(const grmhd_grid* g, const grmhd_params* p, const double* prims, 
     R.code = (int8_t*)(r->mem + L.off_code);
     R.fail_list = (int32_t*)(r->mem + L.off_fail);
     R.slow_list = (int32_t*)(r->mem + L.off_slow);
-    R.geo_uniform = (g->n3 % 64) == 0;
+    // the row path (waves of 64 lanes along one phi row, the metric by scalar loads) can serve the
+    // run when at most a third of the lanes repeat a cell of the row: every n3 that is a multiple
+    // of 64, and other n3 >= 48 close enough above one; the engine decides (Engine::rebuild)
+    R.nkc = (g->n3 + 63) / 64;
+    R.row_ok = g->n3 >= 48 && 3 * (R.nkc * 64 - g->n3) <= R.nkc * 64;
+    R.geo_uniform = R.row_ok && g->n3 % 64 == 0;
     R.var = (RunVar*)(r->mem + L.off_var);
     R.fd_n2 = make_fastdiv(g->n2);
     R.fd_n3 = make_fastdiv(g->n3);
-    R.fd_kc = make_fastdiv(R.geo_uniform ? g->n3 / 64 : 1);
+    R.fd_kc = make_fastdiv(R.row_ok ? R.nkc : 1);
     R.fd_row[0] = make_fastdiv(1);
     R.fd_row[1] = make_fastdiv(g->n1 + 1);
     R.fd_row[2] = make_fastdiv(g->n2 + 1);
@@ -365,9 +370,13 @@ struct Engine {
     long long t_n[NTK] = {0};
     Shape shape[NK];
     // the X2 and X3 face kernels run on two side streams, forked from and joined back into the
-    // run's stream (parallel branches of the captured graph); default priority like the main one
+    // run's stream (parallel branches of the captured graph); default priority like the main one.
+    // Made on first need: only when the runs hold >= 2^20 cells (the overlap pays on big grids; a
+    // lone small run would pay the streams' creation and gain nothing).
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+    bool fork_on = false;
+    int64_t cells = 0;
 
     ~Engine() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -396,6 +405,10 @@ struct Engine {
         }
         const char* ng = std::getenv("GRMHD_NO_GRAPH");
         use_graph = !(ng && ng[0] == '1');
+        return GRMHD_OK;
+    }
+    int make_side_streams() {
+        if (side[0]) return GRMHD_OK;
         HIPCHK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
         for (int x = 0; x < 2; ++x) {
             HIPCHK(hipStreamCreateWithFlags(&side[x], hipStreamNonBlocking));
@@ -415,23 +428,61 @@ struct Engine {
                 const int x = kind - KB_F1, d = x % 3 + 1;
                 const bool uni = (x / 3) % 2 == 0, ppm = x >= 6;
                 if (uni != (bool)R.geo_uniform || ppm != (bool)R.ppm) return 0;
+                const int64_t kl = uni ? (int64_t)R.nkc * 64 : n3;   // lanes per row
                 // marching X1/X2 kernels: one wave per segment of seg faces, 64 k and a row
-                if (uni && !ppm && d == 1) return R.act1 ? march_waves(R, 1, seg) * 64 : 0;
-                if (uni && !ppm && d == 2) return R.act2 ? march_waves(R, 2, seg) * 64 : 0;
-                if (d == 1) return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * n3 : 0;
-                if (d == 2) return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * n3 : 0;
-                return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * n3 : 0;
+                if (uni && !ppm && (d == 1 || d == 2)) {
+                    if (!(d == 1 ? R.act1 : R.act2)) return 0;
+                    RunDev Rs = R;
+                    Rs.mseg[d - 1] = seg;
+                    return march_waves(Rs, d) * 64;
+                }
+                if (d == 1) return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * kl : 0;
+                if (d == 2) return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * kl : 0;
+                return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * kl : 0;
             }
             // uniform-metric update: workgroups of bs/64 waves on consecutive j (n2 padded to a
             // multiple of that)
-            case KB_UPD: return R.geo_uniform ? n1 * ((n2 + bs / 64 - 1) / (bs / 64) * (bs / 64)) * n3 : 0;
+            case KB_UPD: return R.geo_uniform ? n1 * ((n2 + bs / 64 - 1) / (bs / 64) * (bs / 64)) * R.nkc * 64 : 0;
             // edge EMFs: runs with at least two active directions
             case KB_EMF: return (R.act1 + R.act2 + R.act3 >= 2) ? (n1 + 1) * (n2 + 1) * n3 : 0;
             default: return R.geo_uniform ? 0 : n1 * n2 * n3;
         }
     }
+    // Row path and march segments for the current set of runs.  A run whose n3 is not a multiple
+    // of 64 leaves some lanes of its rows repeating cells: worth it when the runs together fill the
+    // chip (>= 2^20 cells), not for a lone small run, which the one-face kernels spread over more
+    // waves.  The marches keep the launch shape's segment unless the runs together would then get
+    // fewer than ~4096 waves (about four per SIMD).
+    int mseg_eff[2] = {16, 16};
+    void plan_row_path() {
+        cells = 0;
+        for (Run* r : runs) cells += (int64_t)r->h.n1 * r->h.n2 * r->h.n3;
+        for (Run* r : runs) {
+            RunDev& R = r->h;
+            R.geo_uniform = R.row_ok && (R.n3 % 64 == 0 || cells >= (int64_t(1) << 20));
+        }
+        for (int d = 1; d <= 2; ++d) {
+            const int kind = d == 1 ? KB_F1 : KB_F2;
+            int64_t units = 0;
+            for (Run* r : runs)
+                if (r->h.geo_uniform && !r->h.ppm) units += march_units(r->h, d);
+            const int64_t cap = units / 4096;
+            const int seg = shape[kind].seg;
+            mseg_eff[d - 1] = (int)(seg < cap ? seg : (cap > 1 ? cap : 1));
+        }
+        for (Run* r : runs) {
+            r->h.mseg[0] = mseg_eff[0];
+            r->h.mseg[1] = mseg_eff[1];
+        }
+    }
     int rebuild() {
         drop_graph();
+        plan_row_path();
+        fork_on = cells >= (int64_t(1) << 20);
+        if (fork_on) {
+            const int rc = make_side_streams();
+            if (rc) return rc;
+        }
         const int n = (int)runs.size();
         if (n > cap) {
             if (d_runs) (void)hipFree(d_runs);
@@ -448,7 +499,8 @@ struct Engine {
             int acc = 0;
             for (int r = 0; r < n; ++r) {
                 boff[kind * (cap + 1) + r] = acc;
-                const int64_t ne = elems(runs[r]->h, kind, shape[kind].bs, shape[kind].seg);
+                const int64_t ne = elems(runs[r]->h, kind, shape[kind].bs,
+                                         kind == KB_F1 ? mseg_eff[0] : (kind == KB_F2 ? mseg_eff[1] : shape[kind].seg));
                 acc += (int)((ne + shape[kind].bs - 1) / shape[kind].bs);
             }
             boff[kind * (cap + 1) + n] = acc;
@@ -498,7 +550,7 @@ struct Engine {
             // face kernels: one direction after another while timing each kernel, otherwise X1 on
             // the run's stream and X2, X3 on the side streams (independent: each reads the stage
             // input and writes its own face array and CFL slot)
-            const bool fork = !timing;
+            const bool fork = fork_on && !timing;
             if (fork) {
                 HIPCHK(hipEventRecord(fork_ev, st));
                 for (int x = 0; x < 2; ++x) HIPCHK(hipStreamWaitEvent(side[x], fork_ev, 0));
@@ -513,7 +565,7 @@ struct Engine {
                     const bool uni = v & 1, ppm = v >> 1;
                     const int k = flux_kind(d, uni, ppm);
                     launch_flux(d, d_runs, boff(k), n, nblk[k], which, stage == 1, 0, uni, ppm, shape[k].bs,
-                                shape[k].sched, shape[k].seg, sd);
+                                shape[k].sched, sd);
                 }
                 mark(TK_FLUX1 + d - 1);
             }
@@ -1065,7 +1117,7 @@ int grmhd_debug_fluxes(grmhd_ctx* c, int32_t d, double* F, double* cmax) {
     const int64_t nface = (int64_t)(d == 1 ? R.n1 + 1 : R.n1 + 2 * R.act1) * (d == 2 ? R.n2 + 1 : R.n2 + 2 * R.act2) * R.n3;
     const int fbs = E.shape[kind].bs;
     launch_flux(d, E.d_runs, E.boff(kind), 1, (int)((nface + fbs - 1) / fbs), 0, 1, 1, 0, R.ppm, fbs,
-                E.shape[kind].sched, E.shape[kind].seg, st);
+                E.shape[kind].sched, st);
     const int64_t n = (int64_t)NCS * (R.n1 + (d == 1)) * (R.n2 + (d == 2)) * (R.n3 + (d == 3));
     double* dF = nullptr;
     HIPCHK(hipMalloc(&dF, n * 8));

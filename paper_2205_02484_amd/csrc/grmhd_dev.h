@@ -61,11 +61,15 @@ struct RunDev {
     int32_t act1, act2, act3;
     int32_t mks, riemann;
     int32_t c2p_maxit, fixup_rounds;
-    int32_t geo_uniform;        // n3 % 64 == 0: a wave's 64 cells share (r, theta)
+    int32_t geo_uniform;        // row path: a wave is 64 lanes of one phi row (its cells share
+                                //   (r, theta)), lane l of chunk c at k = (64 c + l) mod n3
     int32_t ppm;                // reconstruction: 0 PLM with the MC limiter, 1 PPM
     int32_t pole_fix;           // MKS: cells next to each pole whose u~2 is interpolated to zero
+    int32_t nkc;                // row path: 64-lane chunks per row, ceil(n3 / 64)
+    int32_t mseg[2];            // row path: faces per wave segment of the X1 and X2 marches
+    int32_t row_ok;             // the row path can serve this run (the engine decides geo_uniform)
     int32_t pad_;
-    FastDiv fd_n2, fd_n3, fd_kc;  // divisors n2, n3, n3/64 (the last only when geo_uniform)
+    FastDiv fd_n2, fd_n3, fd_kc;  // divisors n2, n3, nkc (the last only on the row path)
     FastDiv fd_row[4];          // [d]: row length of the flux-face rows: n1 + 1, n2 + 1, n2 + 2 act2
     FastDiv fd_jg[3];           // [l]: number of j groups of 2^l rows, ceil(n2 / 2^l)
     int64_t s1, s2, vs;         // cell strides: i, j (k stride 1); variable stride

@@ -20,22 +20,31 @@ void launch_geometry(const GeoArgs& A, hipStream_t st);
 void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int bs, int sched,
                   hipStream_t st);
 // ent = 1 also computes and stores the entropy component (diagnostics); the stage chain uses 0.
-// uni = 1 (with ent = 0): the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
+// uni = 1 (with ent = 0): the block table covers only row-path runs (scalar metric loads)
 // ppm = 1: the block table covers only PPM runs (0: only PLM runs)
-// uni = 1, ppm = 0, ent = 0: X1 and X2 faces are marched along the normal in segments of `seg`
-// faces per wave (march_waves gives the wave count), X3 faces take neighbouring cells from lanes
+// uni = 1, ppm = 0, ent = 0: X1 and X2 faces are marched along the normal in segments of each
+// run's mseg faces per wave (march_waves gives the wave count), X3 faces take neighbouring cells
+// from lanes
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int uni, int ppm, int bs, int sched, int seg, hipStream_t st);
-// waves of the marching face kernel along d in {1, 2} for a run with n3 % 64 == 0
-inline int64_t march_waves(const RunDev& R, int d, int seg) {
+                 int ent, int uni, int ppm, int bs, int sched, hipStream_t st);
+// faces x rows x chunks of the march along d in {1, 2}: its waves with one-face segments
+inline int64_t march_units(const RunDev& R, int d) {
     const int64_t nf = (d == 1 ? R.n1 : R.n2) + 1;
     const int64_t nrow = d == 1 ? R.n2 + 2 * R.act2 : R.n1 + 2 * R.act1;
-    return (nf + seg - 1) / seg * nrow * (R.n3 / 64);
+    return nf * nrow * R.nkc;
+}
+// waves of the marching face kernel along d in {1, 2} for a run on the row path (segments of
+// R.mseg[d - 1] faces)
+inline int64_t march_waves(const RunDev& R, int d) {
+    const int64_t nf = (d == 1 ? R.n1 : R.n2) + 1;
+    const int64_t nrow = d == 1 ? R.n2 + 2 * R.act2 : R.n1 + 2 * R.act1;
+    const int64_t seg = R.mseg[d - 1];
+    return (nf + seg - 1) / seg * nrow * R.nkc;
 }
 // flux-CT edge EMFs of every run with two or more active directions, over (n1+1)(n2+1)n3 sites
 void launch_emf(const RunDev* runs, const int* boff, int nruns, int nblocks, int bs, int sched, hipStream_t st);
 void launch_dt(const RunDev* runs, int nruns, hipStream_t st);
-// uni = 1: the block table covers only runs with n3 % 64 == 0 (scalar metric loads)
+// uni = 1: the block table covers only row-path runs (scalar metric loads)
 void launch_update(const RunDev* runs, const int* boff, int nruns, int nblocks, int stage, int uni, int bs,
                    int sched, hipStream_t st);
 void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st);

@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     const int j0 = D == 2 ? 0 : -R.act2;
     const int ni = D == 1 ? n1 + 1 : n1 + 2 * R.act1;
     const int nj = D == 2 ? n2 + 1 : n2 + 2 * R.act2;
-    // rows of n3 faces.  With n3 % 64 == 0 a wave is one row, and X1-face rows go i fastest so
+    // rows of n3 faces.  On the row path a wave is one row, and X1-face rows go i fastest so
     // that the stencil planes are read close together in time; otherwise a wave spans several
     // rows, and every direction goes j fastest, since consecutive j rows are adjacent in memory
     // (i-fastest rows would spread a wave over planes ~(n2+6) n3 doubles apart: with n3 = 1 every
@@ -423,11 +423,13 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     const uint32_t nrows = (uint32_t)ni * (uint32_t)nj;
     uint32_t row, k;
     if (UNI) {
-        // n3 % 64 == 0: a wave is 64 consecutive k of one row, decomposed once per wave
+        // row path: a wave is 64 lanes of one row, decomposed once per wave; lanes past the row's
+        // end wrap to its start and repeat faces other lanes form (same values stored twice)
         const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(
             (int)((uint32_t)(bl - boff[r]) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
         row = fdiv(wv, R.fd_kc);
-        k = ((wv - row * (uint32_t)(n3 >> 6)) << 6) + (threadIdx.x & 63);
+        k = ((wv - row * (uint32_t)R.nkc) << 6) + (threadIdx.x & 63);
+        if (k >= (uint32_t)n3) k -= (uint32_t)n3;
     } else {
         const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
         row = fdiv(e, R.fd_n3);
@@ -451,7 +453,7 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
     if (do_cfl) cfl_max<D>(R, cw);
 }
 
-// Face fluxes along D in {1, 2} for PLM runs with n3 % 64 == 0, marched along the face normal: a
+// Face fluxes along D in {1, 2} for PLM runs on the row path, marched along the face normal: a
 // wave holds 64 consecutive k of one transverse row and walks a segment of `seg` faces along D,
 // carrying the last two cells and the left state of its next face in registers, so each face
 // loads one new cell (8 values) where the one-face kernel loads four, and each cell's MC slope is
@@ -459,18 +461,19 @@ __global__ __launch_bounds__(256) void k_flux(const RunDev* __restrict__ runs, c
 // Waves are numbered 64-k chunk fastest, then transverse row, then segment.
 template <int D>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_flux_march(const RunDev* __restrict__ runs, const int* __restrict__ boff,
-                                                    int nruns, int which, int do_cfl, int sched, int seg) {
+                                                    int nruns, int which, int do_cfl, int sched) {
     static_assert(D == 1 || D == 2, "marching runs along X1 or X2");
     const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int r = find_run(boff, nruns, bl);
     const RunDev& R = runs[r];
     if (!R.var->active) return;
     const int n1 = R.n1, n2 = R.n2;
-    const uint32_t nkc = (uint32_t)R.n3 >> 6;
+    const uint32_t nkc = (uint32_t)R.nkc;
     const int act = D == 1 ? R.act2 : R.act1;             // transverse halo rows for flux-CT
     const int ntr = D == 1 ? n2 : n1;                     // interior transverse rows
     const uint32_t nrow = (uint32_t)(ntr + 2 * act);
     const int nf = (D == 1 ? n1 : n2) + 1;                // faces along D
+    const int seg = R.mseg[D - 1];
     const uint32_t nseg = (uint32_t)((nf + seg - 1) / seg);
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(
         (int)((uint32_t)(bl - boff[r]) * (blockDim.x >> 6) + (threadIdx.x >> 6)));
@@ -478,7 +481,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint32_t sg = t / nrow, row = t - sg * nrow;
     double cw = 0.0;
     if (sg < nseg) {
-        const int k = (int)(kc << 6) + (int)(threadIdx.x & 63);
+        int k = (int)(kc << 6) + (int)(threadIdx.x & 63);
+        if (k >= R.n3) k -= R.n3;                         // a repeated face of the row
         const int a = (int)sg * seg, b = min(a + seg, nf);
         const int tr = (int)row - act;                    // j (D = 1) or i (D = 2)
         const bool counts = tr >= 0 && tr < ntr;          // halo rows do not enter the CFL step
@@ -551,10 +555,12 @@ __device__ __forceinline__ double lane_read(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// X3 face fluxes of PLM runs with n3 % 64 == 0: a wave is 64 consecutive k of one (i, j) row and
-// its face k - 1/2 needs cells k-2 .. k+1.  Each lane loads its own cell and one edge cell (lane
-// 0: k0-1, lane 1: k0-2, lane 63: k0+64, periodic in k; the rest reload their own), and takes
-// its neighbours' cells from the adjacent lanes: two loads per primitive instead of four.  The
+// X3 face fluxes of PLM runs on the row path: a wave is 64 lanes of one (i, j) row, lane l of chunk
+// c at k = (64 c + l) mod n3, and its face k - 1/2 needs cells k-2 .. k+1.  The row is periodic, so
+// adjacent lanes hold neighbouring k also where the lanes wrap past the row's end (those lanes
+// repeat faces of the row's start).  Each lane loads its own cell and one edge cell (lane 0:
+// k0-1, lane 1: k0-2, lane 63: k0+64, periodic in k; the rest reload their own), and takes its
+// neighbours' cells from the adjacent lanes: two loads per primitive instead of four.  The
 // arithmetic is that of k_flux<3> face for face (bit for bit).
 __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                                      int nruns, int which, int do_cfl, int sched) {
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ 
     const RunDev& R = runs[r];
     if (!R.var->active) return;
     const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
-    const uint32_t nkc = (uint32_t)n3 >> 6;
+    const uint32_t nkc = (uint32_t)R.nkc;
     const uint32_t nj = (uint32_t)(n2 + 2 * R.act2);
     const uint32_t nrows = (uint32_t)(n1 + 2 * R.act1) * nj;
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(
@@ -574,7 +580,10 @@ __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ 
         const uint32_t qi = row / nj;
         const int i = (int)qi - R.act1, j = (int)(row - qi * nj) - R.act2;
         const int lane = (int)(threadIdx.x & 63);
-        const int k0 = (int)(kc << 6), k = k0 + lane;
+        const int k0 = (int)(kc << 6);
+        int k = k0 + lane;
+        if (k >= n3) k -= n3;            // past the row's end: the row is periodic, so lane
+                                         // neighbours stay k neighbours (repeated faces)
         const uint32_t base = (uint32_t)cell_index(R, i, j, 0);
         int ke = k;
         if (lane == 0) ke = k0 - 1;
@@ -918,9 +927,9 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k
     for (int q = 0; q < NPR; ++q) gst(Pout + q * R.vs, (uint32_t)ci, P[q]);
 }
 
-// UNI: the launch covers only runs whose n3 is a multiple of 64 (a wave's cells share (r, theta),
-// metric by scalar loads); the engine keeps a separate block table for the other runs.  One code
-// path per instantiation keeps the register count at 4 waves per SIMD.
+// UNI: the launch covers only row-path runs (a wave's cells share (r, theta), metric by scalar
+// loads; lanes past the row's end do nothing); the engine keeps a separate block table for the
+// other runs.  One code path per instantiation keeps the register count low.
 template <int STAGE, bool UNI>
 __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                                 int nruns, int sched) {
@@ -936,11 +945,12 @@ __global__ __launch_bounds__(256) void k_update(const RunDev* __restrict__ runs,
         const uint32_t lw = blockDim.x == 256 ? 2u : (blockDim.x == 128 ? 1u : 0u);
         const uint32_t eb = (uint32_t)(bl - boff[r]);
         const uint32_t t = fdiv(eb, R.fd_kc);
-        const uint32_t kc = eb - t * (uint32_t)(R.n3 >> 6);
+        const uint32_t kc = eb - t * (uint32_t)R.nkc;
         const uint32_t i = fdiv(t, R.fd_jg[lw]);
         const int j = (int)(((t - i * (uint32_t)((R.n2 + (1 << lw) - 1) >> lw)) << lw) + wv);
         if (j >= R.n2) return;
         const int k = (int)(kc << 6) + (int)(threadIdx.x & 63);
+        if (k >= R.n3) return;                            // lanes past the row's end
         update_fast<UNI, STAGE>(R, (int)i, j, k);
     } else {
         const uint32_t e = (uint32_t)(bl - boff[r]) * blockDim.x + threadIdx.x;
@@ -1286,11 +1296,11 @@ static void flux_dir(int d, const RunDev* runs, const int* boff, int nruns, int 
 }
 
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
-                 int ent, int uni, int ppm, int bs, int sched, int seg, hipStream_t st) {
+                 int ent, int uni, int ppm, int bs, int sched, hipStream_t st) {
     if (nblocks <= 0) return;
     if (uni && !ppm && !ent) {
-        if (d == 1) k_flux_march<1><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched, seg);
-        else if (d == 2) k_flux_march<2><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched, seg);
+        if (d == 1) k_flux_march<1><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else if (d == 2) k_flux_march<2><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
         else k_flux3_lanes<<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
     } else if (ent) {
         if (ppm) flux_dir<true, false, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);

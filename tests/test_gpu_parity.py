@@ -231,10 +231,12 @@ def _run_graph(G, c, P, nsteps, **over):
 
 
 @pytest.mark.parametrize("recon", ["plm", "ppm"])
-@pytest.mark.parametrize("shape", [(24, 16, 64), (20, 12, 128)])
+@pytest.mark.parametrize("shape", [(24, 16, 64), (20, 12, 128), (20, 12, 48), (16, 10, 100)])
 def test_ten_steps_on_the_uniform_metric_path(G, recon, shape):
-    """n3 a multiple of 64: the instantiation the 256^3 benchmark runs (scalar metric loads,
-    X1-face rows i-fastest, update workgroups on consecutive j), ten graph-replayed CFL steps."""
+    """The row path, which the 256^3 benchmark runs (a wave is one phi row: scalar metric loads,
+    marching and lane-shift face kernels, update workgroups on consecutive j), ten graph-replayed
+    CFL steps.  n3 = 48 and 100 are on it too: the lanes of a row's last chunk wrap past its end
+    (the face kernels repeat faces of the row's start, the update leaves those lanes idle)."""
     c = _small3d(n1=shape[0], n2=shape[1], n3=shape[2], seed=31, recon=recon)
     P = make_torus(c)
     print("case", recon, shape, flush=True)
