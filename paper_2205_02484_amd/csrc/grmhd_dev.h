@@ -110,6 +110,14 @@ __device__ __forceinline__ void gst(double* base, uint32_t e, double v) {
     *(g_double*)((g_char*)base + e * 8u) = v;
 }
 
+// Streaming forms for data a kernel touches once (non-temporal hint: do not keep it in the caches).
+__device__ __forceinline__ double gld_nt(const double* base, uint32_t e) {
+    return __builtin_nontemporal_load((const g_double*)((const g_char*)base + e * 8u));
+}
+__device__ __forceinline__ void gst_nt(double* base, uint32_t e, double v) {
+    __builtin_nontemporal_store(v, (g_double*)((g_char*)base + e * 8u));
+}
+
 // Wave-uniform read of a table no stage kernel writes (the metric) through the constant address
 // space: the load is a scalar load even after vector stores of the same kernel, which a
 // global-space load in a loop with stores is not (the compiler cannot rule out a clobber).

@@ -322,7 +322,7 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-            if (ENT || q != 4 + D) gst(F + flux_store_slot<D, ENT>(q) * R.vs, (uint32_t)ci, 0.0);
+            if (ENT || q != 4 + D) gst_nt(F + flux_store_slot<D, ENT>(q) * R.vs, (uint32_t)ci, 0.0);
         return 0.0;
     }
     const double* __restrict__ P = which ? R.Ph : R.P;
@@ -366,7 +366,7 @@ __device__ __forceinline__ double flux_face(const RunDev& R, int i, int j, int k
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (!ENT && q == 4 + D) continue;  // normal field component: not stored by the stage chain
-        gst(F + flux_store_slot<D, ENT>(q) * R.vs, (uint32_t)ci, out[q]);
+        gst_nt(F + flux_store_slot<D, ENT>(q) * R.vs, (uint32_t)ci, out[q]);
     }
     if (D != 1 && (i < 0 || i >= n1)) return 0.0;
     if (D != 2 && (j < 0 || j >= n2)) return 0.0;
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 // polar axis: no flux through the pole
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    if (q != 4 + D) gst(F + flux_slot<D>(q) * vs, c, 0.0);
+                    if (q != 4 + D) gst_nt(F + flux_slot<D>(q) * vs, c, 0.0);
             } else {
                 Geo G;
                 load_geo_k(R.gf[D], R.gpts,
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 const double cwf = riemann_face<D, false>(R, Pl, Pr, G, out);
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    if (q != 4 + D) gst(F + flux_slot<D>(q) * vs, c, out[q]);
+                    if (q != 4 + D) gst_nt(F + flux_slot<D>(q) * vs, c, out[q]);
                 if (counts) cw = fmax(cw, cwf);
             }
 #pragma unroll
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ 
         double* __restrict__ F = R.F[3];
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (q != 7) gst(F + flux_slot<3>(q) * vs, base + (uint32_t)k, out[q]);
+            if (q != 7) gst_nt(F + flux_slot<3>(q) * vs, base + (uint32_t)k, out[q]);
         if (i >= 0 && i < n1 && j >= 0 && j < n2) cw = cwf;
     }
     if (do_cfl) cfl_max<3>(R, cw);
@@ -714,18 +714,18 @@ __global__ __launch_bounds__(256) void k_emf(const RunDev* __restrict__ runs, co
         const double* F1b2 = R.F[1] + flux_slot<1>(6) * vs;
         const double* F2b1 = R.F[2] + flux_slot<2>(5) * vs;
         const double v = axis ? 0.0 : 0.25 * (gld(F1b2, c - s2) + gld(F1b2, c) - gld(F2b1, c - s1) - gld(F2b1, c));
-        gst(R.F[1] + FS_EMF * vs, c, v);
+        gst_nt(R.F[1] + FS_EMF * vs, c, v);
     }
     if (R.act1 && R.act3 && j < n2) {
         const double* F3b1 = R.F[3] + flux_slot<3>(5) * vs;
         const double* F1b3 = R.F[1] + flux_slot<1>(7) * vs;
-        gst(R.F[3] + FS_EMF * vs, c, 0.25 * (gld(F3b1, c - s1) + gld(F3b1, c) - gld(F1b3, ckm) - gld(F1b3, c)));
+        gst_nt(R.F[3] + FS_EMF * vs, c, 0.25 * (gld(F3b1, c - s1) + gld(F3b1, c) - gld(F1b3, ckm) - gld(F1b3, c)));
     }
     if (R.act2 && R.act3 && (int)i < n1) {
         const double* F2b3 = R.F[2] + flux_slot<2>(7) * vs;
         const double* F3b2 = R.F[3] + flux_slot<3>(6) * vs;
         const double v = axis ? 0.0 : 0.25 * (gld(F2b3, ckm) + gld(F2b3, c) - gld(F3b2, c - s2) - gld(F3b2, c));
-        gst(R.F[2] + FS_EMF * vs, c, v);
+        gst_nt(R.F[2] + FS_EMF * vs, c, v);
     }
 }
 
@@ -851,7 +851,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     const double* __restrict__ Pn = R.P;
     const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) Pg[q] = gld(Pin + q * vs, ci);
+    for (int q = 0; q < NPR; ++q) Pg[q] = gld_nt(Pin + q * vs, ci);
     prim_state(Pg, G, gam, sg);
     if (stage == 1) {
         // the stage input is P^n itself: U(P^n) comes from the same state
@@ -859,7 +859,7 @@ __device__ __forceinline__ void stage_state(const RunDev& R, int i, int j, int k
     } else {
         double P0[NPR];
 #pragma unroll
-        for (int q = 0; q < NPR; ++q) P0[q] = gld(Pn + q * vs, ci);
+        for (int q = 0; q < NPR; ++q) P0[q] = gld_nt(Pn + q * vs, ci);
         St s0;
         prim_state(P0, G, gam, s0);
         flux_of<0>(P0, s0, G, ENT ? s0.p * pow(P0[0], 1.0 - gam) : 0.0, U);
@@ -924,7 +924,7 @@ __device__ __forceinline__ void update_fast(const RunDev& R, int i, int j, int k
     double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
     R.code[ci] = 0;
 #pragma unroll
-    for (int q = 0; q < NPR; ++q) gst(Pout + q * R.vs, (uint32_t)ci, P[q]);
+    for (int q = 0; q < NPR; ++q) gst_nt(Pout + q * R.vs, (uint32_t)ci, P[q]);
 }
 
 // UNI: the launch covers only row-path runs (a wave's cells share (r, theta), metric by scalar
