@@ -132,10 +132,29 @@ def ensemble_legs(args, stream):
     sjobs = serve.served_jobs(rate_hz=rate, duration_s=args.serve_seconds, seed=5)
     print(f"[bench] served stream: {len(sjobs)} jobs over {args.serve_seconds:.0f} s at {rate:.3f}/s",
           file=sys.stderr, flush=True)
-    srv = serve.serve(sjobs, steps_per_launch=20, stream=stream,
+    srv = serve.serve(sjobs, steps_per_launch=20, stream=stream, max_active_cells=args.serve_cap_cells,
                       log=lambda m: print(m, file=sys.stderr, flush=True))
     print(f"[bench] served p50 {srv['p50_s']:.2f} s p99 {srv['p99_s']:.2f} s, {srv['zu_per_s']:.3e} ZU/s",
           file=sys.stderr, flush=True)
+    vs_plain = None
+    if args.plain_seconds > 0:
+        # the first plain_seconds of the same arrivals, served by the batched loop and by the plain
+        # baseline (one job at a time, first come first served, the plain stepper)
+        def head():
+            return [j for j in serve.served_jobs(rate_hz=rate, duration_s=args.serve_seconds, seed=5)
+                    if j.arrival < args.plain_seconds]
+        hb = serve.serve(head(), steps_per_launch=20, stream=stream, max_active_cells=args.serve_cap_cells)
+        print(f"[bench] first {args.plain_seconds:.0f} s of the stream ({hb['jobs']} jobs): batched p50 "
+              f"{hb['p50_s']:.2f} s p99 {hb['p99_s']:.2f} s; plain", file=sys.stderr, flush=True)
+        hp = serve.serve_plain(head(), stream=stream)
+        print(f"[bench] plain p50 {hp['p50_s']:.2f} s p99 {hp['p99_s']:.2f} s, {hp['seconds']:.1f} s",
+              file=sys.stderr, flush=True)
+        vs_plain = {"arrivals_s": args.plain_seconds, "jobs": hb["jobs"],
+                    "batched": {"p50_s": hb["p50_s"], "p99_s": hb["p99_s"], "mean_s": hb["mean_s"],
+                                "seconds": hb["seconds"], "zu_per_s": hb["zu_per_s"]},
+                    "plain": {"p50_s": hp["p50_s"], "p99_s": hp["p99_s"], "mean_s": hp["mean_s"],
+                              "seconds": hp["seconds"], "zu_per_s": hp["zu_per_s"]},
+                    "plain_is": "same arrivals, one job at a time in arrival order, plain stepper"}
     return {
         "workload": "48 seeded tori (24 2D 64^2-192^2, 24 3D 48-96 x 48 x 48), spin U[0,0.98], "
                     "gamma {4/3,13/9,5/3}, beta {30,100,300}, r_max U[10,30]",
@@ -147,8 +166,9 @@ def ensemble_legs(args, stream):
         "served": {"duration_s": args.serve_seconds, "rate_hz": rate, "load": 0.8, "jobs": srv["jobs"],
                    "p50_s": srv["p50_s"], "p99_s": srv["p99_s"], "mean_s": srv["mean_s"],
                    "zu_per_s": srv["zu_per_s"], "seconds": srv["seconds"], "passes": srv["passes"],
-                   "max_steps_per_pass": 20,
+                   "max_steps_per_pass": 20, "max_active_cells": args.serve_cap_cells,
                    "mix": "2D 128^2 or 3D N^3 (N in [64,160]), 100-2000 steps each"},
+        "served_vs_plain": vs_plain,
     }
 
 
@@ -167,6 +187,12 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble and served-stream legs")
     ap.add_argument("--ensemble-steps", type=int, default=500, help="steps of each of the 48 ensemble tori")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="length of the served arrival stream")
+    ap.add_argument("--serve-cap-cells", type=int, default=1 << 21,
+                    help="served loop: admit a job only while the active jobs hold at most this many cells "
+                         "(a larger job runs alone); 0: admit whatever fits the memory budget")
+    ap.add_argument("--plain-seconds", type=float, default=10.0,
+                    help="arrivals of the stream's head served both batched and by the plain one-at-a-time "
+                         "baseline (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size kernel that "
                          "scales the HBM counters of a profiler pass)")

@@ -164,12 +164,17 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
           log: Optional[Callable[[str], None]] = None, batch=None,
           make_input: Callable[[TorusConfig], np.ndarray] = make_torus,
           clock: Callable[[], float] = time.perf_counter,
-          sleep: Callable[[float], None] = time.sleep) -> Dict[str, float]:
+          sleep: Callable[[float], None] = time.sleep,
+          max_active_cells: int = 0) -> Dict[str, float]:
     """Replay an arrival stream in real time with continuous batching.
 
     Arrived jobs wait in a FIFO queue; every pass admits, in order, each queued job whose
     footprint fits the remaining budget (smaller jobs may pass a large head), advances all active
-    jobs, and retires finished ones (fetch + release).  A pass lasts as many steps as the active
+    jobs, and retires finished ones (fetch + release).  With max_active_cells > 0 a job is also
+    admitted only while the active jobs' cells stay within that many (a job larger than the cap
+    runs when none is active): the active set is kept near what fills the chip, so large jobs run
+    close to alone in arrival order instead of sharing the GPU with every arrival, and small ones
+    still batch.  A pass lasts as many steps as the active
     job closest to completion still needs, at most `steps_per_launch`: a job is retired at the end
     of the pass in which it takes its last step, never a partial pass later.  Latency is arrival ->
     finished on the host.  `batch`, `make_input`, `clock` and `sleep` can be replaced (host-side
@@ -195,7 +200,11 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
             queue.append(j)
             nxt += 1
         still = []
+        cells = sum(a.cfg.zones for a in active.values())
         for j in queue:
+            if max_active_cells > 0 and active and cells + j.cfg.zones > max_active_cells:
+                still.append(j)
+                continue
             h = b.admit(j.cfg, inputs[j.jid], j.nsteps)
             if h is None:
                 still.append(j)
@@ -204,6 +213,7 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
             j.admitted = time_now() - t0
             active[h] = j
             left[h] = j.nsteps
+            cells += j.cfg.zones
             del inputs[j.jid]
         queue = still
         if active:
@@ -235,3 +245,44 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
             "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
             "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
             "mean_s": float(lat.mean()) if len(lat) else math.nan}
+
+
+def _run_one_plain(job: Job, P: np.ndarray, stream=None) -> None:
+    ctx = grmhd.Context(job.cfg, P, stream=stream)
+    ctx.steps(job.nsteps)
+    ctx.get_prims()                          # the result back on the host, as serve() fetches it
+    ctx.close()
+
+
+def serve_plain(jobs: List[Job], stream=None,
+                make_input: Callable[[TorusConfig], np.ndarray] = make_torus,
+                run_one: Optional[Callable[[Job, np.ndarray], None]] = None,
+                clock: Callable[[], float] = time.perf_counter,
+                sleep: Callable[[float], None] = time.sleep) -> Dict[str, float]:
+    """The plain baseline for serve(): the same arrival stream in real time, one job at a time
+    in arrival order, each run to completion alone with the plain stepper (no batching, no
+    overlap).  Latency is arrival -> finished on the host, as in serve().  `run_one`, `clock` and
+    `sleep` can be replaced (host-side tests)."""
+    if run_one is None:
+        def run_one(j, P):
+            _run_one_plain(j, P, stream)
+    pending = sorted(jobs, key=lambda j: j.arrival)
+    t0 = clock()
+    zu = 0
+    lat = []
+    for j in pending:
+        wait = j.arrival - (clock() - t0)
+        if wait > 0:
+            sleep(wait)
+        P = make_input(j.cfg)
+        run_one(j, P)
+        j.done = clock() - t0
+        lat.append(j.done - j.arrival)
+        zu += j.zone_updates
+    el = clock() - t0
+    lat = np.array(lat)
+    return {"jobs": len(lat), "seconds": el, "zone_updates": zu, "zu_per_s": zu / el if el > 0 else math.nan,
+            "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
+            "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
+            "mean_s": float(lat.mean()) if len(lat) else math.nan}
+

@@ -118,3 +118,47 @@ def test_a_pass_ends_when_the_nearest_job_takes_its_last_step():
     assert abs(jobs[0].done - jobs[0].admitted - 0.025) < 1e-12
     assert abs(jobs[1].done - jobs[1].admitted - 0.037) < 1e-12
     assert res["passes"] == 5      # 10, 10, 5 (job 0 done), 10, 2 (job 1 done)
+
+
+def test_plain_baseline_serves_one_job_at_a_time_in_arrival_order():
+    """serve_plain: each job starts when it has arrived and the previous one is done, runs for
+    its own service time, and its latency is done - arrival (a single-server FIFO queue)."""
+    clock = FakeClock()
+    order = []
+
+    def run_one(j, P):
+        order.append(j.jid)
+        clock.t += 1e-3 * j.nsteps           # 1 ms of the fake clock per step, alone on the GPU
+
+    jobs = [_job(2, 64, 300, arrival=0.2), _job(0, 64, 500, arrival=0.0), _job(1, 64, 100, arrival=0.1),
+            _job(3, 64, 100, arrival=2.0)]
+    res = serve.serve_plain(jobs, make_input=lambda c: None, run_one=run_one, clock=clock, sleep=clock.sleep)
+    assert order == [0, 1, 2, 3]
+    done = {j.jid: j.done for j in jobs}
+    assert abs(done[0] - 0.5) < 1e-12 and abs(done[1] - 0.6) < 1e-12 and abs(done[2] - 0.9) < 1e-12
+    assert abs(done[3] - 2.1) < 1e-12                   # the server idles until job 3 arrives
+    lat = sorted(j.done - j.arrival for j in jobs)
+    assert res["jobs"] == 4 and res["p50_s"] == np.percentile(lat, 50)
+
+
+def test_active_cell_cap_keeps_large_jobs_apart_and_lets_small_ones_batch():
+    """max_active_cells: the active jobs' cells never exceed the cap unless a single job is larger
+    than the cap (then it runs alone); jobs that fit under the cap run together."""
+    clock = FakeClock()
+    fb = FakeBatch(budget=10 ** 9, clock=clock)
+    seen = []
+    orig = fb.advance
+
+    def advance(steps):
+        seen.append(sorted(fb.jobs[h][0] for h in fb.jobs if not fb.jobs[h][2]))
+        orig(steps)
+    fb.advance = advance
+    cap = 2 * 64 * 64
+    jobs = [_job(0, 100, 30, 0.0), _job(1, 64, 30, 0.0), _job(2, 64, 30, 0.0), _job(3, 64, 30, 0.0)]
+    res = serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
+                      sleep=clock.sleep, max_active_cells=cap)
+    assert res["jobs"] == 4
+    for active in seen:
+        assert sum(active) <= cap or len(active) == 1
+    assert [100 * 100] in seen                          # the large job alone
+    assert [64 * 64, 64 * 64] in seen                   # two small ones together
