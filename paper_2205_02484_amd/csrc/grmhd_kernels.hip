@@ -1004,8 +1004,106 @@ __global__ __launch_bounds__(256) void k_update_slow(const RunDev* __restrict__ 
 // failed cells of each run -- the 4-cross average when all four are valid, else the 4-diagonal
 // average, else the average of whichever of the 8 are valid; neighbours outside the interior do
 // not count.  Cells fixed in a round become valid in the next one; a cell still failed after the
-// last round takes rho, u, u~ from the stage input and keeps its field.  One workgroup per run.
+// last round takes rho, u, u~ from the stage input and keeps its field.
+// The first round reads only cells that were valid before it, so k_fixup_first (averaging) and
+// k_fixup_settle (floors) spread it over FIXB workgroups per run; k_fixup (one workgroup per run)
+// runs the later rounds, each of which needs the previous one complete, for the cells still failed.
+// Most failures are isolated cells that the first round fixes.
 // ------------------------------------------------------------------------------------------
+
+constexpr int FIXB = 64;
+
+// averaging step of one round for failed cell e (code -1): the average goes to Pout and the cell
+// is marked pending (4: valid from the next round on); a cell with no valid neighbour stays -1
+__device__ __forceinline__ void fixup_average(const RunDev& R, double* __restrict__ Pout, int e) {
+    const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+    const int64_t vs = R.vs;
+    const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+    const int64_t ci = cell_index(R, i, j, k);
+    if (R.code[ci] != -1) return;
+    const int di[8] = {1, -1, 0, 0, 1, 1, -1, -1};
+    const int dj[8] = {0, 0, 1, -1, 1, -1, 1, -1};
+    bool ok[8];
+    int nvalid = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int ii = i + di[s], jj = j + dj[s];
+        bool v = ii >= 0 && ii < n1 && jj >= 0 && jj < n2;
+        if (v) {
+            const int8_t c = R.code[cell_index(R, ii, jj, k)];
+            v = c >= 0 && c <= 3;
+        }
+        ok[s] = v;
+        nvalid += v;
+    }
+    if (nvalid == 0) return;
+    const bool cross = ok[0] && ok[1] && ok[2] && ok[3];
+    const bool diag = ok[4] && ok[5] && ok[6] && ok[7];
+    double avg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int s0 = cross ? 0 : 4;
+    if (cross || diag) {
+        for (int s = s0; s < s0 + 4; ++s) {
+            const int64_t cn = cell_index(R, i + di[s], j + dj[s], k);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) avg[q] += Pout[q * vs + cn];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) avg[q] *= 0.25;
+    } else {
+        for (int s = 0; s < 8; ++s) {
+            if (!ok[s]) continue;
+            const int64_t cn = cell_index(R, i + di[s], j + dj[s], k);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) avg[q] += Pout[q * vs + cn];
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) avg[q] /= (double)nvalid;
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Pout[q * vs + ci] = avg[q];
+    R.code[ci] = 4;
+}
+
+// second step of a round for cell e: a pending cell becomes valid (code 3) after the floors;
+// returns whether it was pending
+__device__ __forceinline__ bool fixup_settle(const RunDev& R, double* __restrict__ Pout, int e) {
+    const int n2 = R.n2, n3 = R.n3;
+    const int64_t vs = R.vs;
+    const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+    const int64_t ci = cell_index(R, i, j, k);
+    if (R.code[ci] != 4) return false;
+    R.code[ci] = 3;
+    const int64_t gi = geo_index(R, i, j);
+    Geo G;
+    load_geo(R.gc, R.gpts, gi, G);
+    double P[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) P[q] = Pout[q * vs + ci];
+    apply_floors(R, G, R.gc[G_RHOFL * R.gpts + gi], R.gc[G_UFL * R.gpts + gi], P);
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = P[q];
+    return true;
+}
+
+// averaging step of the first round, FIXB workgroups per run striding over its failed cells
+__global__ __launch_bounds__(256) void k_fixup_first(const RunDev* __restrict__ runs, int nruns, int stage) {
+    const RunDev& R = runs[blockIdx.x / FIXB];
+    if (!R.var->active || R.fixup_rounds < 1) return;
+    const int nf = R.var->fail_count;
+    double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
+    for (int x = (blockIdx.x % FIXB) * blockDim.x + threadIdx.x; x < nf; x += FIXB * blockDim.x)
+        fixup_average(R, Pout, R.fail_list[x]);
+}
+
+// floors step of the first round, FIXB workgroups per run
+__global__ __launch_bounds__(256) void k_fixup_settle(const RunDev* __restrict__ runs, int nruns, int stage) {
+    const RunDev& R = runs[blockIdx.x / FIXB];
+    if (!R.var->active || R.fixup_rounds < 1) return;
+    const int nf = R.var->fail_count;
+    double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
+    for (int x = (blockIdx.x % FIXB) * blockDim.x + threadIdx.x; x < nf; x += FIXB * blockDim.x)
+        fixup_settle(R, Pout, R.fail_list[x]);
+}
 
 __global__ __launch_bounds__(256) void k_fixup(const RunDev* __restrict__ runs, int nruns, int stage) {
     const RunDev& R = runs[blockIdx.x];
@@ -1014,84 +1112,36 @@ __global__ __launch_bounds__(256) void k_fixup(const RunDev* __restrict__ runs, 
     const int nf = active ? V->fail_count : 0;
     __shared__ int left_s;
     if (nf > 0) {
-        const int n1 = R.n1, n2 = R.n2, n3 = R.n3;
+        const int n2 = R.n2, n3 = R.n3;
         const int64_t vs = R.vs;
         double* __restrict__ Pout = stage == 1 ? R.Ph : R.P;
         const double* __restrict__ Pin = stage == 1 ? R.P : R.Ph;
-        if (threadIdx.x == 0) left_s = nf;
+        // the first round ran in k_fixup_first and k_fixup_settle: gather the cells still failed
+        // into the slow list (finished with by now); a round's result does not depend on the order
+        // of its cells, so the later rounds walk only those
+        __shared__ int nleft_s;
+        if (threadIdx.x == 0) nleft_s = 0;
         __syncthreads();
-        for (int round = 0; round < R.fixup_rounds; ++round) {
+        for (int x = threadIdx.x; x < nf; x += blockDim.x) {
+            const int e = R.fail_list[x];
+            const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
+            if (R.code[cell_index(R, i, j, k)] == -1) R.slow_list[atomicAdd(&nleft_s, 1)] = e;
+        }
+        __syncthreads();
+        const int nl = nleft_s;
+        if (threadIdx.x == 0) left_s = nl;
+        __syncthreads();
+        for (int round = 1; round < R.fixup_rounds; ++round) {
             if (left_s == 0) break;
-            for (int x = threadIdx.x; x < nf; x += blockDim.x) {
-                const int e = R.fail_list[x];
-                const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
-                const int64_t ci = cell_index(R, i, j, k);
-                if (R.code[ci] != -1) continue;
-                const int di[8] = {1, -1, 0, 0, 1, 1, -1, -1};
-                const int dj[8] = {0, 0, 1, -1, 1, -1, 1, -1};
-                bool ok[8];
-                int nvalid = 0;
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int ii = i + di[s], jj = j + dj[s];
-                    bool v = ii >= 0 && ii < n1 && jj >= 0 && jj < n2;
-                    if (v) {
-                        const int8_t c = R.code[cell_index(R, ii, jj, k)];
-                        v = c >= 0 && c <= 3;
-                    }
-                    ok[s] = v;
-                    nvalid += v;
-                }
-                if (nvalid == 0) continue;
-                const bool cross = ok[0] && ok[1] && ok[2] && ok[3];
-                const bool diag = ok[4] && ok[5] && ok[6] && ok[7];
-                double avg[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                const int s0 = cross ? 0 : 4;
-                if (cross || diag) {
-                    for (int s = s0; s < s0 + 4; ++s) {
-                        const int64_t cn = cell_index(R, i + di[s], j + dj[s], k);
-#pragma unroll
-                        for (int q = 0; q < 5; ++q) avg[q] += Pout[q * vs + cn];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) avg[q] *= 0.25;
-                } else {
-                    for (int s = 0; s < 8; ++s) {
-                        if (!ok[s]) continue;
-                        const int64_t cn = cell_index(R, i + di[s], j + dj[s], k);
-#pragma unroll
-                        for (int q = 0; q < 5; ++q) avg[q] += Pout[q * vs + cn];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 5; ++q) avg[q] /= (double)nvalid;
-                }
-#pragma unroll
-                for (int q = 0; q < 5; ++q) Pout[q * vs + ci] = avg[q];
-                R.code[ci] = 4;  // pending: valid from the next round on
-            }
+            for (int x = threadIdx.x; x < nl; x += blockDim.x) fixup_average(R, Pout, R.slow_list[x]);
             __syncthreads();
-            for (int x = threadIdx.x; x < nf; x += blockDim.x) {
-                const int e = R.fail_list[x];
-                const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
-                const int64_t ci = cell_index(R, i, j, k);
-                if (R.code[ci] != 4) continue;
-                R.code[ci] = 3;
-                const int64_t gi = geo_index(R, i, j);
-                Geo G;
-                load_geo(R.gc, R.gpts, gi, G);
-                double P[NPR];
-#pragma unroll
-                for (int q = 0; q < NPR; ++q) P[q] = Pout[q * vs + ci];
-                apply_floors(R, G, R.gc[G_RHOFL * R.gpts + gi], R.gc[G_UFL * R.gpts + gi], P);
-#pragma unroll
-                for (int q = 0; q < NPR; ++q) Pout[q * vs + ci] = P[q];
-                atomicSub(&left_s, 1);
-            }
+            for (int x = threadIdx.x; x < nl; x += blockDim.x)
+                if (fixup_settle(R, Pout, R.slow_list[x])) atomicSub(&left_s, 1);
             __syncthreads();
         }
         int mine = 0;
-        for (int x = threadIdx.x; x < nf; x += blockDim.x) {
-            const int e = R.fail_list[x];
+        for (int x = threadIdx.x; x < nl; x += blockDim.x) {
+            const int e = R.slow_list[x];
             const int k = e % n3, t = e / n3, j = t % n2, i = t / n2;
             const int64_t ci = cell_index(R, i, j, k);
             if (R.code[ci] != -1) continue;
@@ -1339,6 +1389,8 @@ void launch_update_slow(const RunDev* runs, int nruns, int stage, hipStream_t st
 }
 
 void launch_fixup(const RunDev* runs, int nruns, int stage, hipStream_t st) {
+    k_fixup_first<<<nruns * FIXB, 256, 0, st>>>(runs, nruns, stage);
+    k_fixup_settle<<<nruns * FIXB, 256, 0, st>>>(runs, nruns, stage);
     k_fixup<<<nruns, 256, 0, st>>>(runs, nruns, stage);
 }
 

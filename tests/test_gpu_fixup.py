@@ -112,3 +112,34 @@ def test_unfixed_cells_keep_the_corner_divergence(G, rounds):
     dx = [(math.log(cfg.r_out) - math.log(cfg.r_in)) / cfg.n1, 1 / cfg.n2]
     div = corner_divb(Pg, gd[..., None], dx, 2)
     assert np.abs(div).max() < 1e-13 * np.abs(P1[5:7] * gd[None, ..., None]).max() / min(dx)
+
+
+@pytest.mark.parametrize("frac,rounds,left", [(0.03, 3, 0), (0.3, 1, 127), (0.6, 2, 21)])
+def test_dense_random_failures_match_the_oracle(G, frac, rounds, left):
+    """Many failed cells spread over the run (3 %, 30 % and 60 % of a 64 x 48 x 16 torus, plus
+    5 x 5 blocks): the first round runs over many workgroups, the later rounds over the cells it
+    left; codes, cells left unfixed (counts from the oracle) and every primitive agree with the
+    oracle."""
+    c = TorusConfig(n1=64, n2=48, n3=16, r_out=60.0, gam=13.0 / 9.0, delta=0.04, seed=11, cfl=0.45)
+    P = make_torus(c)
+    rng = np.random.default_rng(9)
+    code = np.zeros((c.n1, c.n2, c.n3), dtype=np.int8)
+    code[rng.random(code.shape) < frac] = -1
+    for _ in range(12):
+        i, j, k = rng.integers(0, c.n1 - 5), rng.integers(0, c.n2 - 5), rng.integers(0, c.n3)
+        code[i:i + 5, j:j + 5, k] = -1
+    Pin = P.copy()
+    Pin[0:2] *= 1.0 + 0.01 * rng.random(P.shape[1:])
+    Pout = P * (1.0 + 1e-3 * rng.standard_normal(P.shape))
+    Pout[0:2] = np.abs(Pout[0:2])
+    Pout[0:5, code == -1] = np.nan
+    ctx = G.Context(c, P, fixup_max_rounds=rounds)
+    Pg, cg, left_g = ctx.debug_fixup(Pout, Pin, code)
+    ctx.close()
+    cfg = orc.make_cfg(c, fixup_max_rounds=rounds)
+    Po, co, left_o = orc.fixups(cfg, Pout.copy(), Pin, code.copy())
+    assert left_o == left
+    assert np.array_equal(cg, co)
+    assert left_g == left_o
+    assert np.isfinite(Pg).all()
+    assert_parity(Pg, Po, 1e-14)
