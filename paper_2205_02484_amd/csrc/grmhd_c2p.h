@@ -88,7 +88,7 @@ __device__ __forceinline__ double resid1d(const Inv& q, int which, double x) {
 // Brent's bracketing root finder: inverse quadratic / secant steps accepted only while they
 // shrink the bracket fast enough, bisection otherwise; stops when half the bracket is below
 // 2 eps |x| + atol/2.  Returns false without a sign change or on a non-finite residual.
-__device__ __noinline__ bool brent1d(const Inv& q, int which, double lo, double hi, double atol, double* root) {
+__device__ __forceinline__ bool brent1d(const Inv& q, int which, double lo, double hi, double atol, double* root) {
     double a = lo, b = hi;
     double fa = resid1d(q, which, a), fb = resid1d(q, which, b);
     if (!isfinite(fa) || !isfinite(fb)) return false;
@@ -214,7 +214,7 @@ __device__ __forceinline__ int invert_energy(const Inv& q, const Geo& G, double 
     return finish_energy(q, G, W, v2, P) ? 1 : -2;
 }
 
-__device__ __noinline__ int invert_entropy(const Inv& q, const Geo& G, double* P) {
+__device__ __forceinline__ int invert_entropy(const Inv& q, const Geo& G, double* P) {
     if (!(q.D > 0.0) || !(q.ent > 0.0)) return -1;
     double v2;
     if (!brent1d(q, 1, 0.0, V2MAX, 1e-20, &v2)) return -1;
@@ -249,7 +249,7 @@ __device__ __forceinline__ int invert_cell(const double* U, const double* Pg, co
 }
 
 // Floors, magnetisation ceilings and the Lorentz cap on an inverted (or fixed) cell.
-__device__ __noinline__ void ceiling_reinvert(const RunDev& R, const Geo& G, double* P, double drho, double du) {
+__device__ __forceinline__ void ceiling_reinvert(const RunDev& R, const Geo& G, double* P, double drho, double du) {
     St s;
     prim_state(P, G, R.gam, s);
     double U[NCS];
