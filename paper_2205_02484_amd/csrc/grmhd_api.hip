@@ -451,15 +451,19 @@ struct Engine {
     // Row path and march segments for the current set of runs.  A run whose n3 is not a multiple
     // of 64 leaves some lanes of its rows repeating cells: worth it when the runs together fill the
     // chip (>= 2^20 cells), not for a lone small run, which the one-face kernels spread over more
-    // waves.  The marches keep the launch shape's segment unless the runs together would then get
-    // fewer than ~4096 waves (about four per SIMD).
+    // waves.  Such a PLM run gets the same bits from the row path's marching and lane-shift face
+    // kernels as from the one-face kernels it takes alone; a PPM run would take the scalar-metric
+    // one-face kernels, whose last bits differ from the per-lane-metric ones in a few cells, so a
+    // ragged-n3 PPM run stays on the general path in any company.  The marches keep the launch
+    // shape's segment unless the runs together would then get fewer than ~4096 waves (about four
+    // per SIMD).
     int mseg_eff[2] = {16, 16};
     void plan_row_path() {
         cells = 0;
         for (Run* r : runs) cells += (int64_t)r->h.n1 * r->h.n2 * r->h.n3;
         for (Run* r : runs) {
             RunDev& R = r->h;
-            R.geo_uniform = R.row_ok && (R.n3 % 64 == 0 || cells >= (int64_t(1) << 20));
+            R.geo_uniform = R.row_ok && (R.n3 % 64 == 0 || (cells >= (int64_t(1) << 20) && !R.ppm));
         }
         for (int d = 1; d <= 2; ++d) {
             const int kind = d == 1 ? KB_F1 : KB_F2;
