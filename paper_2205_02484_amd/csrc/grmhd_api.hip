@@ -369,23 +369,29 @@ struct Engine {
     double t_ms[NTK] = {0};
     long long t_n[NTK] = {0};
     Shape shape[NK];
-    // the X2 and X3 face kernels run on two side streams, forked from and joined back into the
-    // run's stream (parallel branches of the captured graph); default priority like the main one.
-    // Made on first need: only when the runs hold >= 2^20 cells (the overlap pays on big grids; a
-    // lone small run would pay the streams' creation and gain nothing).
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+    // The row-path X2 and X3 face kernels run on side streams 0 and 1, and every general-path
+    // kernel (the face kernels and the update of the runs off the row path, small ones in a mixed
+    // batch) on side stream 2, forked from and joined back into the run's stream (parallel
+    // branches of the captured graph); default priority like the main one.  Made on first need:
+    // only when the runs hold >= 2^20 cells (the overlap pays on big grids; a lone small run would
+    // pay the streams' creation and gain nothing).
+    static constexpr int NSIDE = 3;
+    hipStream_t side[NSIDE] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[NSIDE] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork2_ev = nullptr, join2_ev = nullptr;
     bool fork_on = false;
     int64_t cells = 0;
 
     ~Engine() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         drop_graph();
-        for (int x = 0; x < 2; ++x) {
+        for (int x = 0; x < NSIDE; ++x) {
             if (join_ev[x]) (void)hipEventDestroy(join_ev[x]);
             if (side[x]) (void)hipStreamDestroy(side[x]);
         }
         if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (fork2_ev) (void)hipEventDestroy(fork2_ev);
+        if (join2_ev) (void)hipEventDestroy(join2_ev);
         if (d_runs) (void)hipFree(d_runs);
         if (d_boff) (void)hipFree(d_boff);
         if (own_stream && st) (void)hipStreamDestroy(st);
@@ -410,7 +416,9 @@ struct Engine {
     int make_side_streams() {
         if (side[0]) return GRMHD_OK;
         HIPCHK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
-        for (int x = 0; x < 2; ++x) {
+        HIPCHK(hipEventCreateWithFlags(&fork2_ev, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&join2_ev, hipEventDisableTiming));
+        for (int x = 0; x < NSIDE; ++x) {
             HIPCHK(hipStreamCreateWithFlags(&side[x], hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&join_ev[x], hipEventDisableTiming));
         }
@@ -557,24 +565,24 @@ struct Engine {
             const bool fork = fork_on && !timing;
             if (fork) {
                 HIPCHK(hipEventRecord(fork_ev, st));
-                for (int x = 0; x < 2; ++x) HIPCHK(hipStreamWaitEvent(side[x], fork_ev, 0));
+                for (int x = 0; x < NSIDE; ++x) HIPCHK(hipStreamWaitEvent(side[x], fork_ev, 0));
             }
             for (int d = 1; d <= 3; ++d) {
                 int any = 0;
                 for (int v = 0; v < 4; ++v) any += nblk[flux_kind(d, v & 1, v >> 1)] > 0;
                 if (!any) continue;
-                const hipStream_t sd = (fork && d > 1) ? side[d - 2] : st;
                 mark(TK_FLUX1 + d - 1);
                 for (int v = 0; v < 4; ++v) {
                     const bool uni = v & 1, ppm = v >> 1;
                     const int k = flux_kind(d, uni, ppm);
+                    const hipStream_t sd = !fork ? st : (!uni ? side[2] : (d > 1 ? side[d - 2] : st));
                     launch_flux(d, d_runs, boff(k), n, nblk[k], which, stage == 1, 0, uni, ppm, shape[k].bs,
                                 shape[k].sched, sd);
                 }
                 mark(TK_FLUX1 + d - 1);
             }
             if (fork) {
-                for (int x = 0; x < 2; ++x) {
+                for (int x = 0; x < NSIDE; ++x) {
                     HIPCHK(hipEventRecord(join_ev[x], side[x]));
                     HIPCHK(hipStreamWaitEvent(st, join_ev[x], 0));
                 }
@@ -588,9 +596,19 @@ struct Engine {
             launch_emf(d_runs, boff(KB_EMF), n, nblk[KB_EMF], shape[KB_EMF].bs, shape[KB_EMF].sched, st);
             mark(TK_EMF);
             mark(TK_UPDATE);
+            // the row-path and the other runs' updates touch different runs: two branches
+            const bool fork2 = fork && nblk[KB_UPD] > 0 && nblk[KB_UPDN] > 0;
+            if (fork2) {
+                HIPCHK(hipEventRecord(fork2_ev, st));
+                HIPCHK(hipStreamWaitEvent(side[2], fork2_ev, 0));
+            }
             launch_update(d_runs, boff(KB_UPD), n, nblk[KB_UPD], stage, 1, shape[KB_UPD].bs, shape[KB_UPD].sched, st);
             launch_update(d_runs, boff(KB_UPDN), n, nblk[KB_UPDN], stage, 0, shape[KB_UPDN].bs, shape[KB_UPDN].sched,
-                          st);
+                          fork2 ? side[2] : st);
+            if (fork2) {
+                HIPCHK(hipEventRecord(join2_ev, side[2]));
+                HIPCHK(hipStreamWaitEvent(st, join2_ev, 0));
+            }
             mark(TK_UPDATE);
             mark(TK_SLOW);
             launch_update_slow(d_runs, n, stage, st);
