@@ -555,13 +555,15 @@ __device__ __forceinline__ double lane_read(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// X3 face fluxes of PLM runs on the row path: a wave is 64 lanes of one (i, j) row, lane l of chunk
-// c at k = (64 c + l) mod n3, and its face k - 1/2 needs cells k-2 .. k+1.  The row is periodic, so
-// adjacent lanes hold neighbouring k also where the lanes wrap past the row's end (those lanes
-// repeat faces of the row's start).  Each lane loads its own cell and one edge cell (lane 0:
-// k0-1, lane 1: k0-2, lane 63: k0+64, periodic in k; the rest reload their own), and takes its
-// neighbours' cells from the adjacent lanes: two loads per primitive instead of four.  The
-// arithmetic is that of k_flux<3> face for face (bit for bit).
+// X3 face fluxes of runs on the row path: a wave is 64 lanes of one (i, j) row, lane l of chunk c at
+// k = (64 c + l) mod n3, and its face k - 1/2 needs cells k-2 .. k+1 (PLM) or k-3 .. k+2 (PPM).  The
+// row is periodic, so adjacent lanes hold neighbouring k also where the lanes wrap past the row's
+// end (those lanes repeat faces of the row's start).  Each lane loads its own cell and one edge
+// cell (lane 0: k0-1, lane 1: k0-2, lane 63: k0+64, and for PPM lane 2: k0-3, lane 62: k0+65;
+// periodic in k; the rest reload their own), and takes its neighbours' cells from the adjacent
+// lanes: two loads per primitive instead of four (PLM) or six (PPM).  The PLM arithmetic is that
+// of k_flux<3> face for face (bit for bit); the PPM faces agree with it to rounding.
+template <bool PPM>
 __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ runs, const int* __restrict__ boff,
                                                      int nruns, int which, int do_cfl, int sched) {
     const int bl = (sched & 1) ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
@@ -589,6 +591,8 @@ __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ 
         if (lane == 0) ke = k0 - 1;
         else if (lane == 1) ke = k0 - 2;
         else if (lane == 63) ke = k0 + 64;
+        else if (PPM && lane == 2) ke = k0 - 3;
+        else if (PPM && lane == 62) ke = k0 + 65;
         ke = ke < 0 ? ke + n3 : (ke >= n3 ? ke - n3 : ke);
         const uint32_t vs = (uint32_t)R.vs;
         const double* __restrict__ P = which ? R.Ph : R.P;
@@ -603,8 +607,14 @@ __global__ __launch_bounds__(256) void k_flux3_lanes(const RunDev* __restrict__ 
             const double m1 = lane_shr1(e, c);                                     // cell k-1
             const double m2 = lane_shr1(lane_read(e, 1), m1);                      // cell k-2
             const double p1 = lane_shl1(e, c);                                     // cell k+1
-            Pl[q] = m1 + mc_half_slope(m2, m1, c);
-            Pr[q] = c - mc_half_slope(m1, c, p1);
+            if (PPM) {
+                const double m3 = lane_shr1(lane_read(e, 2), m2);                  // cell k-3
+                const double p2 = lane_shl1(lane_read(e, 62), p1);                 // cell k+2
+                ppm_face(m3, m2, m1, c, p1, p2, Pl[q], Pr[q]);
+            } else {
+                Pl[q] = m1 + mc_half_slope(m2, m1, c);
+                Pr[q] = c - mc_half_slope(m1, c, p1);
+            }
         }
         double out[NCS];
         const double cwf = riemann_face<3, false>(R, Pl, Pr, G, out);
@@ -1351,7 +1361,9 @@ void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblo
     if (uni && !ppm && !ent) {
         if (d == 1) k_flux_march<1><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
         else if (d == 2) k_flux_march<2><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
-        else k_flux3_lanes<<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+        else k_flux3_lanes<false><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
+    } else if (uni && ppm && !ent && d == 3) {
+        k_flux3_lanes<true><<<nblocks, bs, 0, st>>>(runs, boff, nruns, which, do_cfl, sched);
     } else if (ent) {
         if (ppm) flux_dir<true, false, true>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
         else flux_dir<true, false, false>(d, runs, boff, nruns, nblocks, which, do_cfl, bs, sched, st);
