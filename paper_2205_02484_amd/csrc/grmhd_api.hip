@@ -444,6 +444,12 @@ struct Engine {
                     Rs.mseg[d - 1] = seg;
                     return march_waves(Rs, d) * 64;
                 }
+                // PPM X1/X2 faces on the row path: one thread per pair of faces along d
+                if (uni && ppm && (d == 1 || d == 2)) {
+                    if (!(d == 1 ? R.act1 : R.act2)) return 0;
+                    const int64_t npair = ((d == 1 ? n1 : n2) + 2) / 2;
+                    return npair * (d == 1 ? n2 + 2 * R.act2 : n1 + 2 * R.act1) * kl;
+                }
                 if (d == 1) return R.act1 ? (n1 + 1) * (n2 + 2 * R.act2) * kl : 0;
                 if (d == 2) return R.act2 ? (n1 + 2 * R.act1) * (n2 + 1) * kl : 0;
                 return R.act3 ? (n1 + 2 * R.act1) * (n2 + 2 * R.act2) * kl : 0;

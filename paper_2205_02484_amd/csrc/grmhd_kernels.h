@@ -24,7 +24,7 @@ void launch_bound(const RunDev* runs, const int* boff, int nruns, int nblocks, i
 // ppm = 1: the block table covers only PPM runs (0: only PLM runs)
 // uni = 1, ppm = 0, ent = 0: X1 and X2 faces are marched along the normal in segments of each
 // run's mseg faces per wave (march_waves gives the wave count), X3 faces take neighbouring cells
-// from lanes; uni = 1, ppm = 1, ent = 0: X3 faces from lanes, X1 and X2 faces one per thread
+// from lanes; uni = 1, ppm = 1, ent = 0: X3 faces from lanes, X1 and X2 faces two per thread
 void launch_flux(int d, const RunDev* runs, const int* boff, int nruns, int nblocks, int which, int do_cfl,
                  int ent, int uni, int ppm, int bs, int sched, hipStream_t st);
 // faces x rows x chunks of the march along d in {1, 2}: its waves with one-face segments
