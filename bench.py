@@ -127,7 +127,9 @@ def ensemble_legs(args, stream):
     bat = serve.run_batched(jobs, steps_per_launch=25, stream=stream, inputs=inputs, autotune_steps=1)
     print(f"[bench] ensemble batched {bat['zu_per_s']:.3e} ZU/s; sequential", file=sys.stderr, flush=True)
     seq = serve.run_sequential(jobs, stream=stream, inputs=inputs)
-    print(f"[bench] ensemble sequential {seq['zu_per_s']:.3e} ZU/s", file=sys.stderr, flush=True)
+    print(f"[bench] ensemble sequential {seq['zu_per_s']:.3e} ZU/s; job latency p50/p99 batched "
+          f"{bat['p50_s']:.2f}/{bat['p99_s']:.2f} s, one after another {seq['p50_s']:.2f}/{seq['p99_s']:.2f} s",
+          file=sys.stderr, flush=True)
     rate = 0.8 * bat["zu_per_s"] / serve.mean_job_zone_updates(seed=5)
     sjobs = serve.served_jobs(rate_hz=rate, duration_s=args.serve_seconds, seed=5)
     print(f"[bench] served stream: {len(sjobs)} jobs over {args.serve_seconds:.0f} s at {rate:.3f}/s",
@@ -162,6 +164,8 @@ def ensemble_legs(args, stream):
         "batched_zu_per_s": bat["zu_per_s"], "batched_seconds": bat["seconds"],
         "sequential_zu_per_s": seq["zu_per_s"], "sequential_seconds": seq["seconds"],
         "batched_over_sequential": bat["zu_per_s"] / seq["zu_per_s"],
+        "job_latency": {"submitted": "all 48 at t = 0", "batched_p50_s": bat["p50_s"], "batched_p99_s": bat["p99_s"],
+                        "sequential_p50_s": seq["p50_s"], "sequential_p99_s": seq["p99_s"]},
         "batched_autotune": bat["autotune"],
         "served": {"duration_s": args.serve_seconds, "rate_hz": rate, "load": 0.8, "jobs": srv["jobs"],
                    "p50_s": srv["p50_s"], "p99_s": srv["p99_s"], "mean_s": srv["mean_s"],

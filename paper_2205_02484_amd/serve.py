@@ -107,28 +107,37 @@ def mean_job_zone_updates(seed: int = 5, samples: int = 4000) -> float:
     return tot / samples
 
 
+def _latency(done: List[float]) -> Dict[str, float]:
+    d = np.array(done)
+    return {"p50_s": float(np.percentile(d, 50)), "p99_s": float(np.percentile(d, 99))} if len(d) else {}
+
+
 def run_sequential(jobs: List[Job], stream=None, inputs: Optional[List[np.ndarray]] = None) -> Dict[str, float]:
-    """Each job alone with the plain stepper (one context at a time)."""
+    """Each job alone with the plain stepper (one context at a time).  Every job counts as
+    submitted at the start; its latency is the time until its run has finished."""
     import torch
     if inputs is None:
         inputs = [make_torus(j.cfg) for j in jobs]
     t0 = time.perf_counter()
     zu = 0
+    done = []
     for j, P in zip(jobs, inputs):
         ctx = grmhd.Context(j.cfg, P, stream=stream)
         ctx.steps(j.nsteps)
         ctx.get_time()                       # waits for the run
         ctx.close()
         zu += j.zone_updates
+        done.append(time.perf_counter() - t0)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el}
+    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el, **_latency(done)}
 
 
 def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
                 keep: Optional[Callable[[Job, np.ndarray], None]] = None,
                 inputs: Optional[List[np.ndarray]] = None, autotune_steps: int = 0) -> Dict[str, float]:
-    """All jobs resident together, advanced in one kernel chain until each is done.  With
+    """All jobs resident together, advanced in one kernel chain until each is done (latency: from the
+    start, when every job is submitted, until it is retired).  With
     autotune_steps > 0 the launch-shape autotuner first runs that many ordinary steps per candidate
     shape on the whole ensemble (they count towards each job's steps and are timed with the rest)."""
     b = grmhd.Batch(stream=stream)
@@ -144,6 +153,7 @@ def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
         by_handle[h] = j
     left = len(jobs)
     zu = 0
+    done = []
     tuned = b.autotune(autotune_steps) if autotune_steps > 0 else ""
     while left:
         b.advance(steps_per_launch)
@@ -154,9 +164,10 @@ def run_batched(jobs: List[Job], steps_per_launch: int = 25, stream=None,
             b.release(h)
             zu += j.zone_updates
             left -= 1
+            done.append(time.perf_counter() - t0)
     el = time.perf_counter() - t0
     b.close()
-    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el,
+    return {"seconds": el, "zone_updates": zu, "zu_per_s": zu / el, **_latency(done),
             "autotune": [ln for ln in tuned.splitlines() if ln.startswith("chosen")]}
 
 
