@@ -230,3 +230,38 @@ def test_batched_ragged_runs_equal_their_solo_runs(G):
                         [int(x) for x in np.argwhere((Pb != Ps).any(axis=0))[:3].ravel()]))
     b.close()
     assert not bad, bad
+
+
+def test_march_segment_length_does_not_change_results(G):
+    """The X1 and X2 face marches walk segments of faces whose length the engine sets from the whole
+    block table (at least ~4096 waves): each of these n3 = 64 runs alone (4290-6402 march units)
+    marches one face per wave; batched (about 20.8k units, >= 2^20 cells) five, with a partial last
+    segment, and the X2 waves numbered segment before row.  Each face's arithmetic is the same, so
+    batched and solo results agree bit for bit."""
+    cfgs = [TorusConfig(n1=n1, n2=64, n3=64, r_out=60.0, spin=0.2, gam=13 / 9, beta=100.0, r_max=12.0,
+                        r_in=6.0, seed=70 + x, recon="plm") for x, n1 in enumerate((64, 72, 80, 96))]
+    assert sum(c.zones for c in cfgs) >= 1 << 20
+    steps = 3
+    solo = []
+    for c in cfgs:
+        ctx = G.Context(c, make_torus(c))
+        ctx.steps(steps)
+        solo.append(ctx.get_prims())
+        ctx.close()
+    b = G.Batch()
+    ids = [b.admit(c, make_torus(c), steps) for c in cfgs]
+    done = set()
+    for _ in range(10):
+        b.advance(steps)
+        done |= set(b.poll())
+        if len(done) == len(ids):
+            break
+    assert done == set(ids)
+    bad = []
+    for jid, c, Ps in zip(ids, cfgs, solo):
+        Pb, _, nb = b.fetch(jid)
+        assert nb == steps
+        if not np.array_equal(Pb, Ps):
+            bad.append((c.n1, int((Pb != Ps).any(axis=0).sum())))
+    b.close()
+    assert not bad, bad
