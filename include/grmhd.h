@@ -235,6 +235,14 @@ int grmhd_batch_poll(grmhd_batch* b, int64_t* done_ids, int32_t cap, int32_t* n_
 /* Copy a job's primitives (host, [8][n1][n2][n3]), time and step count out. */
 int grmhd_batch_fetch(grmhd_batch* b, int64_t job_id, double* prims, double* t, int64_t* nstep);
 
+/* Accretion diagnostics of a job's current state (Sec. 4.2, as grmhd_diag_full: the same horizon
+ * values in *hz and, when `radial` is non-NULL, the same radial profiles radial[6][n1], host and
+ * caller-owned), so that ensemble and served runs report them without leaving the batch.  Ordered
+ * after the work already enqueued on the batch's stream, and waits for it.  ENOTFOUND for an
+ * unknown or released job; EINVAL for a NULL batch or hz, or for a job whose grid is not MKS or does
+ * not reach the horizon. */
+int grmhd_batch_diag_full(grmhd_batch* b, int64_t job_id, grmhd_horizon* hz, double* radial);
+
 /* Free a job's device memory and its slot. */
 int grmhd_batch_release(grmhd_batch* b, int64_t job_id);
 

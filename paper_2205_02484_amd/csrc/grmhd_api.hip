@@ -932,21 +932,21 @@ int grmhd_diag(grmhd_ctx* c, double* mdot, double* phi_b) {
     return GRMHD_OK;
 }
 
-int grmhd_diag_full(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
-    if (!c || !hz) return fail(GRMHD_EINVAL, "NULL argument");
-    const RunDev& R = c->run->h;
-    if (!R.mks || c->run->ih < 0) return fail(GRMHD_EINVAL, "diagnostics need an MKS grid reaching the horizon");
+// Shell sums of one run (a context's or a batch job's) on the stream its work is enqueued on.
+static int diag_full_run(Run* r, hipStream_t st, grmhd_horizon* hz, double* radial) {
+    const RunDev& R = r->h;
+    if (!R.mks || r->ih < 0) return fail(GRMHD_EINVAL, "diagnostics need an MKS grid reaching the horizon");
     const int n1 = R.n1;
     double* d = nullptr;
     HIPCHK(hipMalloc(&d, 6 * (size_t)n1 * sizeof(double)));
     std::vector<double> h(6 * (size_t)n1);
-    launch_diag_shells(R, d, c->eng.st);
+    launch_diag_shells(R, d, st);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->eng.st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->eng.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(GRMHD_EDEVICE, "diag_full: %s", hipGetErrorString(e));
-    const int ih = c->run->ih;
+    const int ih = r->ih;
     hz->mdot = h[0 * n1 + ih];
     hz->phi_b = h[1 * n1 + ih];
     hz->ldot = h[2 * n1 + ih];
@@ -964,6 +964,11 @@ int grmhd_diag_full(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
         }
     }
     return GRMHD_OK;
+}
+
+int grmhd_diag_full(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
+    if (!c || !hz) return fail(GRMHD_EINVAL, "NULL argument");
+    return diag_full_run(c->run, c->eng.st, hz, radial);
 }
 
 int grmhd_diag_full_noalloc(grmhd_ctx* c, grmhd_horizon* hz, double* radial) {
@@ -1318,6 +1323,13 @@ int grmhd_batch_fetch(grmhd_batch* b, int64_t job_id, double* prims, double* t, 
         if (nstep) *nstep = v.nstep;
     }
     return GRMHD_OK;
+}
+
+int grmhd_batch_diag_full(grmhd_batch* b, int64_t job_id, grmhd_horizon* hz, double* radial) {
+    if (!b || !hz) return fail(GRMHD_EINVAL, "NULL argument");
+    Run* r = find_job(b, job_id);
+    if (!r) return fail(GRMHD_ENOTFOUND, "no job %lld", (long long)job_id);
+    return diag_full_run(r, b->eng.st, hz, radial);
 }
 
 int grmhd_batch_release(grmhd_batch* b, int64_t job_id) {

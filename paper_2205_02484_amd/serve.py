@@ -30,6 +30,7 @@ class Job:
     admitted: Optional[float] = None
     done: Optional[float] = None
     handle: Optional[int] = None
+    horizon: Optional[Dict[str, float]] = None   # accretion diagnostics at completion (serve(diagnose=True))
 
     @property
     def zone_updates(self) -> int:
@@ -176,7 +177,7 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
           make_input: Callable[[TorusConfig], np.ndarray] = make_torus,
           clock: Callable[[], float] = time.perf_counter,
           sleep: Callable[[float], None] = time.sleep,
-          max_active_cells: int = 0) -> Dict[str, float]:
+          max_active_cells: int = 0, diagnose: bool = False) -> Dict[str, float]:
     """Replay an arrival stream in real time with continuous batching.
 
     Arrived jobs wait in a FIFO queue; every pass admits, in order, each queued job whose
@@ -188,7 +189,9 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
     still batch.  A pass lasts as many steps as the active
     job closest to completion still needs, at most `steps_per_launch`: a job is retired at the end
     of the pass in which it takes its last step, never a partial pass later.  Latency is arrival ->
-    finished on the host.  `batch`, `make_input`, `clock` and `sleep` can be replaced (host-side
+    finished on the host.  With `diagnose`, each finished job's horizon diagnostics (Sec. 4.2: Mdot,
+    phi_B, Ldot, Edot, the MAD parameter) are taken on the device before its slot is released and
+    kept in `Job.horizon`.  `batch`, `make_input`, `clock` and `sleep` can be replaced (host-side
     tests of the scheduling logic)."""
     b = batch if batch is not None else grmhd.Batch(budget_bytes=budget_bytes, stream=stream)
     time_now = clock
@@ -237,6 +240,8 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
                 j = active.pop(h)
                 left.pop(h, None)
                 b.fetch(h)
+                if diagnose:
+                    j.horizon = b.diag_full(h)[0]
                 b.release(h)
                 j.done = time_now() - t0
                 zu += j.zone_updates

@@ -93,3 +93,39 @@ def test_diagnostics_on_the_hyperexponential_grid(G):
     c = TorusConfig(n1=96, n2=64, n3=1, r_out=5000.0, r_br=400.0, n_x=4, gam=13.0 / 9.0, delta=0.04,
                     seed=17, cfl=0.45)
     _check(G, c, 5)
+
+
+def test_batch_job_diagnostics_equal_the_solo_runs(G):
+    """grmhd_batch_diag_full on the jobs of a batch: each job's horizon values and radial profiles
+    equal those of the same run stepped alone in a context, bit for bit (the batched state equals
+    the solo state bit for bit, and both calls form the shell sums with the same kernel); a released
+    job is reported as ENOTFOUND."""
+    cfgs = [torus_2d_64(),
+            TorusConfig(n1=40, n2=24, n3=16, r_out=60.0, gam=13.0 / 9.0, delta=0.04, seed=11, cfl=0.45)]
+    steps = 4
+    solo = []
+    for c in cfgs:
+        ctx = G.Context(c, make_torus(c))
+        ctx.steps(steps)
+        solo.append((ctx.get_prims(), ctx.diag_full()))
+        ctx.close()
+    b = G.Batch()
+    ids = [b.admit(c, make_torus(c), steps) for c in cfgs]
+    done = set()
+    for _ in range(10):
+        b.advance(steps)
+        done |= set(b.poll())
+        if len(done) == len(ids):
+            break
+    assert done == set(ids)
+    for jid, (Ps, (hzs, rads)) in zip(ids, solo):
+        Pb, _, nb = b.fetch(jid)
+        assert nb == steps and np.array_equal(Pb, Ps)
+        hz, rad = b.diag_full(jid)
+        assert hz == hzs
+        assert np.array_equal(rad, rads, equal_nan=True)
+    b.release(ids[0])
+    with pytest.raises(G.GrmhdError) as ei:
+        b.diag_full(ids[0])
+    assert ei.value.code == G.ENOTFOUND
+    b.close()

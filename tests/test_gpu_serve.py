@@ -1,6 +1,6 @@
 """GPU test of the served request loop: jobs arriving while others run are admitted, all finish,
-and each served result equals the same job run alone (bit for bit: the batched kernels do the same
-arithmetic per run)."""
+and each served result and its horizon diagnostics equal those of the same job run alone (bit for
+bit: the batched kernels do the same arithmetic per run)."""
 import numpy as np
 import pytest
 
@@ -29,16 +29,18 @@ def test_served_stream_results_equal_solo_runs():
         kept[h] = out
         return out
     b.fetch = fetch
-    res = serve.serve(jobs, steps_per_launch=5, batch=b, make_input=make_input)
+    res = serve.serve(jobs, steps_per_launch=5, batch=b, make_input=make_input, diagnose=True)
     assert res["jobs"] == 6
     for j in jobs:
         ctx = grmhd.Context(j.cfg, make_torus(j.cfg))
         ctx.steps(j.nsteps)
         P = ctx.get_prims()
         t, n, _ = ctx.get_time()
+        hz = ctx.diag_full()[0]
         ctx.close()
         Pb, tb, nb = kept[j.handle]
         assert nb == n == j.nsteps
         assert tb == t
         assert np.array_equal(Pb, P)
+        assert j.horizon == hz
     b.close()

@@ -55,6 +55,10 @@ class FakeBatch:
     def fetch(self, h):
         return None
 
+    def diag_full(self, h):
+        assert h in self.jobs, "diagnostics of a released job"
+        return {"mdot": -float(h)}, None
+
     def release(self, h):
         self.used -= self.jobs.pop(h)[0]
 
@@ -162,3 +166,16 @@ def test_active_cell_cap_keeps_large_jobs_apart_and_lets_small_ones_batch():
         assert sum(active) <= cap or len(active) == 1
     assert [100 * 100] in seen                          # the large job alone
     assert [64 * 64, 64 * 64] in seen                   # two small ones together
+
+
+def test_diagnostics_are_taken_before_release_only_when_asked():
+    for diagnose in (False, True):
+        clock = FakeClock()
+        fb = FakeBatch(budget=3 * 64 * 64, clock=clock)
+        jobs = [_job(i, 64, 20 + 5 * i, arrival=0.01 * i) for i in range(5)]
+        serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
+                    sleep=clock.sleep, diagnose=diagnose)
+        if diagnose:
+            assert all(j.horizon == {"mdot": -float(j.handle)} for j in jobs)
+        else:
+            assert all(j.horizon is None for j in jobs)
