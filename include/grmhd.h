@@ -166,6 +166,15 @@ int grmhd_get_prims(grmhd_ctx* ctx, double* out, int32_t out_on_device);
 /* Time, step count and the number of cells left unfixed since init. */
 int grmhd_get_time(grmhd_ctx* ctx, double* t, int64_t* nstep, int64_t* nfail_total);
 
+/* Set the run's time and step count, so that a restart continues the original clock: a context
+ * created by grmhd_init from primitives read back with grmhd_get_prims, given the time and step
+ * count grmhd_get_time reported with them, steps exactly as the uninterrupted run (the RK2 step of
+ * Sec. 2.2 carries nothing from one step to the next but the primitives: it recomputes the
+ * conserved variables from them, and the CFL dt depends only on the current state).  Waits for the
+ * work already enqueued on the context's stream.  EINVAL for a NULL ctx, a non-finite t or
+ * nstep < 0. */
+int grmhd_set_time(grmhd_ctx* ctx, double t, int64_t nstep);
+
 /* Method codes of the last inversion stage, [n1][n2][n3]: 0 NR, 1 Brent W, 2 entropy,
  * 3 fixed by neighbour averaging, -1 left unfixed. */
 int grmhd_get_codes(grmhd_ctx* ctx, int8_t* codes);

@@ -1046,6 +1046,19 @@ int grmhd_get_time(grmhd_ctx* c, double* t, int64_t* nstep, int64_t* nfail_total
     return GRMHD_OK;
 }
 
+int grmhd_set_time(grmhd_ctx* c, double t, int64_t nstep) {
+    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
+    if (!std::isfinite(t) || nstep < 0) return fail(GRMHD_EINVAL, "t must be finite and nstep >= 0");
+    RunVar v;
+    int rc = read_var(c->run, c->eng.st, &v);
+    if (rc) return rc;
+    v.t = t;
+    v.nstep = nstep;
+    HIPCHK(hipMemcpyAsync(c->run->h.var, &v, sizeof(RunVar), hipMemcpyHostToDevice, c->eng.st));
+    HIPCHK(hipStreamSynchronize(c->eng.st));
+    return GRMHD_OK;
+}
+
 int grmhd_get_codes(grmhd_ctx* c, int8_t* codes) {
     if (!c || !codes) return fail(GRMHD_EINVAL, "NULL argument");
     const RunDev& R = c->run->h;

@@ -24,7 +24,7 @@ PLM, PPM = 0, 1
 # exported symbols of include/grmhd.h
 SYMBOLS = [
     "grmhd_params_default", "grmhd_init", "grmhd_step", "grmhd_steps", "grmhd_cons2prim",
-    "grmhd_prim2cons", "grmhd_diag", "grmhd_diag_full", "grmhd_diag_full_noalloc", "grmhd_get_prims", "grmhd_get_time", "grmhd_get_codes",
+    "grmhd_prim2cons", "grmhd_diag", "grmhd_diag_full", "grmhd_diag_full_noalloc", "grmhd_get_prims", "grmhd_get_time", "grmhd_set_time", "grmhd_get_codes",
     "grmhd_debug_fluxes", "grmhd_debug_fixup", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
     "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_autotune", "grmhd_batch_poll",
     "grmhd_batch_fetch", "grmhd_batch_diag_full", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_diag_full_noalloc.restype = ctypes.c_int
     L.grmhd_get_prims.argtypes = [vp, vp, i32]
     L.grmhd_get_time.argtypes = [vp, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    L.grmhd_set_time.argtypes = [vp, ctypes.c_double, i64]
     L.grmhd_get_codes.argtypes = [vp, vp]
     L.grmhd_debug_fluxes.argtypes = [vp, i32, vp, dp]
     L.grmhd_debug_fixup.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64)]
@@ -235,6 +236,9 @@ class Context:
         f = ctypes.c_int64()
         _check(load().grmhd_get_time(self._h, ctypes.byref(t), ctypes.byref(n), ctypes.byref(f)))
         return t.value, n.value, f.value
+
+    def set_time(self, t: float, nstep: int):
+        _check(load().grmhd_set_time(self._h, float(t), int(nstep)))
 
     def get_codes(self):
         out = np.empty(self.shape, dtype=np.int8)

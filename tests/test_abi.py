@@ -45,6 +45,10 @@ def test_host_only_calls_work_without_a_gpu():
     fp = grmhd.footprint_bytes(torus_256cubed())
     # two 8-variable state arrays and three 9-variable flux arrays dominate: ~6 GB at 256^3
     assert 5.5e9 < fp < 7.5e9
+    # argument checks that come before any device work
+    L = grmhd.load()
+    assert L.grmhd_set_time(None, 0.0, 0) == grmhd.EINVAL
+    assert L.grmhd_batch_diag_full(None, 1, None, None) == grmhd.EINVAL
 
 
 def test_binding_structs_match_the_header_layout(tmp_path):
