@@ -171,6 +171,7 @@ def ensemble_legs(args, stream):
                    "p50_s": srv["p50_s"], "p99_s": srv["p99_s"], "mean_s": srv["mean_s"],
                    "zu_per_s": srv["zu_per_s"], "seconds": srv["seconds"], "passes": srv["passes"],
                    "max_steps_per_pass": 20, "max_active_cells": args.serve_cap_cells,
+                   "unfixed_cells": srv["unfixed_cells"],
                    "mix": "2D 128^2 or 3D N^3 (N in [64,160]), 100-2000 steps each"},
         "served_vs_plain": vs_plain,
     }

@@ -244,6 +244,12 @@ int grmhd_batch_poll(grmhd_batch* b, int64_t* done_ids, int32_t cap, int32_t* n_
 /* Copy a job's primitives (host, [8][n1][n2][n3]), time and step count out. */
 int grmhd_batch_fetch(grmhd_batch* b, int64_t job_id, double* prims, double* t, int64_t* nstep);
 
+/* Time, step count and number of cells left unfixed since admission of a job (as grmhd_get_time:
+ * the cells that the fixup rounds of Sec. 2.3 could not repair, so that a served run reports its
+ * numerical failures).  Nullable outputs.  Waits for the work already enqueued on the batch's
+ * stream.  ENOTFOUND for an unknown or released job. */
+int grmhd_batch_get_time(grmhd_batch* b, int64_t job_id, double* t, int64_t* nstep, int64_t* nfail_total);
+
 /* Accretion diagnostics of a job's current state (Sec. 4.2, as grmhd_diag_full: the same horizon
  * values in *hz and, when `radial` is non-NULL, the same radial profiles radial[6][n1], host and
  * caller-owned), so that ensemble and served runs report them without leaving the batch.  Ordered

@@ -1338,6 +1338,19 @@ int grmhd_batch_fetch(grmhd_batch* b, int64_t job_id, double* prims, double* t, 
     return GRMHD_OK;
 }
 
+int grmhd_batch_get_time(grmhd_batch* b, int64_t job_id, double* t, int64_t* nstep, int64_t* nfail_total) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    Run* r = find_job(b, job_id);
+    if (!r) return fail(GRMHD_ENOTFOUND, "no job %lld", (long long)job_id);
+    RunVar v;
+    int rc = read_var(r, b->eng.st, &v);
+    if (rc) return rc;
+    if (t) *t = v.t;
+    if (nstep) *nstep = v.nstep;
+    if (nfail_total) *nfail_total = v.nfail_total;
+    return GRMHD_OK;
+}
+
 int grmhd_batch_diag_full(grmhd_batch* b, int64_t job_id, grmhd_horizon* hz, double* radial) {
     if (!b || !hz) return fail(GRMHD_EINVAL, "NULL argument");
     Run* r = find_job(b, job_id);

@@ -27,7 +27,7 @@ SYMBOLS = [
     "grmhd_prim2cons", "grmhd_diag", "grmhd_diag_full", "grmhd_diag_full_noalloc", "grmhd_get_prims", "grmhd_get_time", "grmhd_set_time", "grmhd_get_codes",
     "grmhd_debug_fluxes", "grmhd_debug_fixup", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
     "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_autotune", "grmhd_batch_poll",
-    "grmhd_batch_fetch", "grmhd_batch_diag_full", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
+    "grmhd_batch_fetch", "grmhd_batch_get_time", "grmhd_batch_diag_full", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
 ]
 
 
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
     L.grmhd_batch_advance.argtypes = [vp, i32]
     L.grmhd_batch_poll.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
     L.grmhd_batch_fetch.argtypes = [vp, i64, vp, dp, ctypes.POINTER(i64)]
+    L.grmhd_batch_get_time.argtypes = [vp, i64, dp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.grmhd_batch_diag_full.argtypes = [vp, i64, ctypes.POINTER(Horizon), vp]
     L.grmhd_batch_release.argtypes = [vp, i64]
     L.grmhd_batch_usage.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -356,6 +357,14 @@ class Batch:
         n = ctypes.c_int64()
         _check(load().grmhd_batch_fetch(self._h, int(jid), _ptr(out), ctypes.byref(t), ctypes.byref(n)))
         return out, t.value, n.value
+
+    def get_time(self, jid: int):
+        """(t, step count, cells left unfixed since admission) of a job."""
+        t = ctypes.c_double()
+        n = ctypes.c_int64()
+        f = ctypes.c_int64()
+        _check(load().grmhd_batch_get_time(self._h, int(jid), ctypes.byref(t), ctypes.byref(n), ctypes.byref(f)))
+        return t.value, n.value, f.value
 
     def diag_full(self, jid: int):
         """Horizon diagnostics (dict) and radial profiles [6][n1] of a job's current state, as

@@ -31,6 +31,7 @@ class Job:
     done: Optional[float] = None
     handle: Optional[int] = None
     horizon: Optional[Dict[str, float]] = None   # accretion diagnostics at completion (serve(diagnose=True))
+    unfixed: Optional[int] = None                # cells the fixups left unfixed over the run (serve())
 
     @property
     def zone_updates(self) -> int:
@@ -189,7 +190,9 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
     still batch.  A pass lasts as many steps as the active
     job closest to completion still needs, at most `steps_per_launch`: a job is retired at the end
     of the pass in which it takes its last step, never a partial pass later.  Latency is arrival ->
-    finished on the host.  With `diagnose`, each finished job's horizon diagnostics (Sec. 4.2: Mdot,
+    finished on the host.  Each finished job's count of cells left unfixed is kept in
+    `Job.unfixed`, the served stream's numerical-failure report.  With `diagnose`, each finished
+    job's horizon diagnostics (Sec. 4.2: Mdot,
     phi_B, Ldot, Edot, the MAD parameter) are taken on the device before its slot is released and
     kept in `Job.horizon`.  `batch`, `make_input`, `clock` and `sleep` can be replaced (host-side
     tests of the scheduling logic)."""
@@ -240,6 +243,7 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
                 j = active.pop(h)
                 left.pop(h, None)
                 b.fetch(h)
+                j.unfixed = b.get_time(h)[2]
                 if diagnose:
                     j.horizon = b.diag_full(h)[0]
                 b.release(h)
@@ -258,6 +262,7 @@ def serve(jobs: List[Job], steps_per_launch: int = 20, budget_bytes: int = 0, st
         b.close()
     lat = np.array([j.done - j.arrival for j in finished])
     return {"jobs": len(finished), "seconds": el, "zone_updates": zu, "zu_per_s": zu / el, "passes": passes,
+            "unfixed_cells": int(sum(j.unfixed or 0 for j in finished)),
             "p50_s": float(np.percentile(lat, 50)) if len(lat) else math.nan,
             "p99_s": float(np.percentile(lat, 99)) if len(lat) else math.nan,
             "mean_s": float(lat.mean()) if len(lat) else math.nan}

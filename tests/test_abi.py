@@ -49,6 +49,7 @@ def test_host_only_calls_work_without_a_gpu():
     L = grmhd.load()
     assert L.grmhd_set_time(None, 0.0, 0) == grmhd.EINVAL
     assert L.grmhd_batch_diag_full(None, 1, None, None) == grmhd.EINVAL
+    assert L.grmhd_batch_get_time(None, 1, None, None, None) == grmhd.EINVAL
 
 
 def test_binding_structs_match_the_header_layout(tmp_path):

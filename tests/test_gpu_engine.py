@@ -300,3 +300,34 @@ def test_restart_from_read_back_primitives_continues_bit_for_bit(G, cfg):
     assert (n6, n3, nr) == (6, 3, 6)
     assert np.array_equal(Pr, P6) and np.array_equal(cr, c6)
     assert tr == t6
+
+
+def test_batch_job_reports_the_cells_left_unfixed(G):
+    """A job's count of cells left unfixed (grmhd_batch_get_time) is its solo run's and the oracle's:
+    the magnetised funnel of the ceiling tests (2D, ceilings and Lorentz cap acting) with no fixup
+    rounds leaves cell failures unfixed over ten steps (20 by the oracle's count); the job's state,
+    clock and count equal the solo run's, and a released job is not found."""
+    from tests._funnel import funnel
+    c, over = funnel("2d", "cap")
+    over = dict(over, fixup_max_rounds=0)
+    P = make_torus(c)
+    _, _, nfo, _ = orc.step(orc.make_cfg(c, **over), P, 10)
+    assert nfo > 0
+    ctx = G.Context(c, P, **over)
+    ctx.steps(10)
+    Ps, (ts, ns, nfs) = ctx.get_prims(), ctx.get_time()
+    ctx.close()
+    b = G.Batch()
+    jid = b.admit(c, P, 10, **over)
+    for _ in range(10):
+        b.advance(10)
+        if jid in b.poll():
+            break
+    tb, nb, nfb = b.get_time(jid)
+    assert (ns, nfs) == (10, nfo) and (nb, nfb) == (10, nfo)
+    assert tb == ts and np.array_equal(b.fetch(jid)[0], Ps)
+    b.release(jid)
+    with pytest.raises(G.GrmhdError) as ei:
+        b.get_time(jid)
+    assert ei.value.code == G.ENOTFOUND
+    b.close()

@@ -35,7 +35,7 @@ def test_served_stream_results_equal_solo_runs():
         ctx = grmhd.Context(j.cfg, make_torus(j.cfg))
         ctx.steps(j.nsteps)
         P = ctx.get_prims()
-        t, n, _ = ctx.get_time()
+        t, n, nfail = ctx.get_time()
         hz = ctx.diag_full()[0]
         ctx.close()
         Pb, tb, nb = kept[j.handle]
@@ -43,4 +43,5 @@ def test_served_stream_results_equal_solo_runs():
         assert tb == t
         assert np.array_equal(Pb, P)
         assert j.horizon == hz
+        assert j.unfixed == nfail
     b.close()

@@ -55,6 +55,10 @@ class FakeBatch:
     def fetch(self, h):
         return None
 
+    def get_time(self, h):
+        assert h in self.jobs, "time of a released job"
+        return 0.0, 0, h % 3
+
     def diag_full(self, h):
         assert h in self.jobs, "diagnostics of a released job"
         return {"mdot": -float(h)}, None
@@ -168,13 +172,15 @@ def test_active_cell_cap_keeps_large_jobs_apart_and_lets_small_ones_batch():
     assert [64 * 64, 64 * 64] in seen                   # two small ones together
 
 
-def test_diagnostics_are_taken_before_release_only_when_asked():
+def test_failure_counts_always_and_diagnostics_when_asked_are_taken_before_release():
     for diagnose in (False, True):
         clock = FakeClock()
         fb = FakeBatch(budget=3 * 64 * 64, clock=clock)
         jobs = [_job(i, 64, 20 + 5 * i, arrival=0.01 * i) for i in range(5)]
-        serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
-                    sleep=clock.sleep, diagnose=diagnose)
+        res = serve.serve(jobs, steps_per_launch=10, batch=fb, make_input=lambda c: None, clock=clock,
+                          sleep=clock.sleep, diagnose=diagnose)
+        assert all(j.unfixed == j.handle % 3 for j in jobs)
+        assert res["unfixed_cells"] == sum(j.handle % 3 for j in jobs)
         if diagnose:
             assert all(j.horizon == {"mdot": -float(j.handle)} for j in jobs)
         else:
