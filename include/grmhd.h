@@ -199,8 +199,9 @@ int grmhd_debug_fixup(grmhd_ctx* ctx, double* pout, const double* pin, int8_t* c
  * on the context's stream around every kernel.  grmhd_kernel_times waits for them and returns
  * the average duration (ms) and launch count per kernel kind, in this order: 0 boundary ghosts,
  * 1-3 face fluxes X1/X2/X3, 4 CFL step, 5 update + Newton-Raphson inversion, 6 fixup,
- * 7 full inversion of the cells the fast path hands over (beta switch, Brent, entropy, ceilings).  Turning timing on or off
- * clears the accumulated figures. */
+ * 7 full inversion of the cells the fast path hands over (beta switch, Brent, entropy, ceilings),
+ * 8 flux-CT edge EMFs (at most 9 kinds are filled).  Turning timing on or off clears the
+ * accumulated figures. */
 int grmhd_kernel_timing(grmhd_ctx* ctx, int32_t on);
 int grmhd_kernel_times(grmhd_ctx* ctx, double* avg_ms, int64_t* launches, int32_t n);
 
@@ -237,6 +238,12 @@ int grmhd_batch_advance(grmhd_batch* b, int32_t steps);
 
 /* Autotuner of the ensemble's launch shapes (see grmhd_autotune); the steps count for the jobs. */
 int grmhd_batch_autotune(grmhd_batch* b, int32_t steps_per_candidate, char* report, int32_t report_len);
+
+/* grmhd_kernel_timing / grmhd_kernel_times for the batch's engine: with timing on, later advances
+ * run every kernel as a plain launch with an event pair on the batch's stream (no graph, no
+ * parallel branches), so each figure is the kernel over all active jobs alone on the device. */
+int grmhd_batch_kernel_timing(grmhd_batch* b, int32_t on);
+int grmhd_batch_kernel_times(grmhd_batch* b, double* avg_ms, int64_t* launches, int32_t n);
 
 /* Waits for the enqueued work, then lists up to `cap` finished jobs not yet reported. */
 int grmhd_batch_poll(grmhd_batch* b, int64_t* done_ids, int32_t cap, int32_t* n_done);

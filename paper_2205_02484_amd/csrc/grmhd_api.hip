@@ -1198,9 +1198,8 @@ int grmhd_autotune(grmhd_ctx* c, int32_t steps_per_candidate, char* report, int3
     return copy_report(r, report, report_len);
 }
 
-int grmhd_kernel_timing(grmhd_ctx* c, int32_t on) {
-    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
-    Engine& E = c->eng;
+// Per-kernel timing of an engine (a context's or a batch's): switching clears the figures.
+static int engine_timing(Engine& E, int32_t on) {
     int rc = E.harvest();
     if (rc) return rc;
     E.timing = on != 0;
@@ -1211,9 +1210,7 @@ int grmhd_kernel_timing(grmhd_ctx* c, int32_t on) {
     return GRMHD_OK;
 }
 
-int grmhd_kernel_times(grmhd_ctx* c, double* avg_ms, int64_t* launches, int32_t n) {
-    if (!c || !avg_ms || n < 0) return fail(GRMHD_EINVAL, "NULL argument");
-    Engine& E = c->eng;
+static int engine_times(Engine& E, double* avg_ms, int64_t* launches, int32_t n) {
     int rc = E.harvest();
     if (rc) return rc;
     for (int k = 0; k < n && k < NTK; ++k) {
@@ -1221,6 +1218,16 @@ int grmhd_kernel_times(grmhd_ctx* c, double* avg_ms, int64_t* launches, int32_t 
         if (launches) launches[k] = E.t_n[k];
     }
     return GRMHD_OK;
+}
+
+int grmhd_kernel_timing(grmhd_ctx* c, int32_t on) {
+    if (!c) return fail(GRMHD_EINVAL, "ctx is NULL");
+    return engine_timing(c->eng, on);
+}
+
+int grmhd_kernel_times(grmhd_ctx* c, double* avg_ms, int64_t* launches, int32_t n) {
+    if (!c || !avg_ms || n < 0) return fail(GRMHD_EINVAL, "NULL argument");
+    return engine_times(c->eng, avg_ms, launches, n);
 }
 
 void grmhd_destroy(grmhd_ctx* c) {
@@ -1279,6 +1286,16 @@ int grmhd_batch_advance(grmhd_batch* b, int32_t steps) {
     if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
     if (steps < 0) return fail(GRMHD_EINVAL, "steps < 0");
     return b->eng.steps(steps);
+}
+
+int grmhd_batch_kernel_timing(grmhd_batch* b, int32_t on) {
+    if (!b) return fail(GRMHD_EINVAL, "batch is NULL");
+    return engine_timing(b->eng, on);
+}
+
+int grmhd_batch_kernel_times(grmhd_batch* b, double* avg_ms, int64_t* launches, int32_t n) {
+    if (!b || !avg_ms || n < 0) return fail(GRMHD_EINVAL, "NULL argument");
+    return engine_times(b->eng, avg_ms, launches, n);
 }
 
 int grmhd_batch_autotune(grmhd_batch* b, int32_t steps_per_candidate, char* report, int32_t report_len) {

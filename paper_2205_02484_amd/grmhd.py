@@ -27,6 +27,7 @@ SYMBOLS = [
     "grmhd_prim2cons", "grmhd_diag", "grmhd_diag_full", "grmhd_diag_full_noalloc", "grmhd_get_prims", "grmhd_get_time", "grmhd_set_time", "grmhd_get_codes",
     "grmhd_debug_fluxes", "grmhd_debug_fixup", "grmhd_kernel_timing", "grmhd_kernel_times", "grmhd_autotune", "grmhd_destroy", "grmhd_last_error", "grmhd_footprint_bytes",
     "grmhd_batch_create", "grmhd_batch_admit", "grmhd_batch_advance", "grmhd_batch_autotune", "grmhd_batch_poll",
+    "grmhd_batch_kernel_timing", "grmhd_batch_kernel_times",
     "grmhd_batch_fetch", "grmhd_batch_get_time", "grmhd_batch_diag_full", "grmhd_batch_release", "grmhd_batch_usage", "grmhd_batch_destroy",
 ]
 
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     L.grmhd_kernel_times.argtypes = [vp, dp, ctypes.POINTER(i64), i32]
     L.grmhd_autotune.argtypes = [vp, i32, ctypes.c_char_p, i32]
     L.grmhd_batch_autotune.argtypes = [vp, i32, ctypes.c_char_p, i32]
+    L.grmhd_batch_kernel_timing.argtypes = [vp, i32]
+    L.grmhd_batch_kernel_times.argtypes = [vp, dp, ctypes.POINTER(i64), i32]
     L.grmhd_destroy.argtypes = [vp]
     L.grmhd_destroy.restype = None
     L.grmhd_last_error.argtypes = []
@@ -344,6 +347,17 @@ class Batch:
         buf = ctypes.create_string_buffer(1 << 16)
         _check(load().grmhd_batch_autotune(self._h, int(steps_per_candidate), buf, len(buf)))
         return buf.value.decode()
+
+    def kernel_timing(self, on: bool):
+        _check(load().grmhd_batch_kernel_timing(self._h, int(bool(on))))
+
+    def kernel_times(self):
+        """{kernel kind: (average ms per launch over all active jobs, launches)}, as Context."""
+        n = len(Context.KERNELS)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(load().grmhd_batch_kernel_times(self._h, ms, cnt, n))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(Context.KERNELS)}
 
     def poll(self, cap: int = 1024):
         ids = (ctypes.c_int64 * cap)()

@@ -331,3 +331,35 @@ def test_batch_job_reports_the_cells_left_unfixed(G):
         b.get_time(jid)
     assert ei.value.code == G.ENOTFOUND
     b.close()
+
+
+def test_batch_kernel_timing_runs_plain_launches_with_equal_results(G):
+    """With kernel timing on, a batch advances by plain launches with an event pair around every
+    kernel (no graph, no parallel branches): every kernel kind its jobs use reports launches and a
+    positive duration, and the jobs' results equal those of the graph-replayed batch bit for bit."""
+    cfgs = _cfgs()[:2]                                  # a 2D and a 3D torus
+    steps = 4
+
+    def run(timing):
+        b = G.Batch()
+        ids = [b.admit(c, make_torus(c), steps) for c in cfgs]
+        if timing:
+            b.kernel_timing(True)
+        done = set()
+        for _ in range(10):
+            b.advance(steps)
+            done |= set(b.poll())
+            if len(done) == len(ids):
+                break
+        assert done == set(ids)
+        out = [b.fetch(j)[0] for j in ids]
+        kt = b.kernel_times() if timing else None
+        b.close()
+        return out, kt
+
+    Pg, _ = run(False)
+    Pt, kt = run(True)
+    assert all(np.array_equal(a, b) for a, b in zip(Pg, Pt))
+    for k in ("bound", "flux1", "flux2", "flux3", "dt", "update", "emf"):
+        assert kt[k][1] > 0 and kt[k][0] > 0.0, (k, kt[k])
+    assert kt["dt"][1] == steps and kt["update"][1] == 2 * steps
